@@ -1,0 +1,477 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix (CPU only).
+
+Each test ties the oracle to something other than itself: closed forms for
+constant velocity, brute-force lattice counts and neighbour enumerations, an
+independently formulated dense-box CTU (gather form), exact conservation,
+exact translation at Courant number 1, the Kalman update, the exact moments of
+a linear flow, and the model definitions of Sec. 5.1.
+"""
+import itertools
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import _ref
+from paper_2508_13986_amd import scenarios as S
+
+EPS = np.finfo(np.float64).eps
+
+
+def _step1(o):
+    """One internal step with an unbounded stop time."""
+    o.step(1e30, 1)
+
+
+# ---------------------------------------------------------------------------
+# Models (Sec. 5.1.1 and 5.1.2)
+# ---------------------------------------------------------------------------
+
+def test_l63_paper_form_is_shifted_standard_form(oracle_mod):
+    """The shifted form of Sec. 5.1.1 with (sigma, b, r) equals the standard form at x3 + r."""
+    sig, b, r = 4.0, 1.0, 48.0
+    o = oracle_mod.Oracle(S._base(3, S.L63, S.lorenz63(sig, r, b, r), 0.5, [0, 0, 0], np.eye(3), 1e-5, 1.0))
+    rng = np.random.default_rng(0)
+    for x in rng.normal(0, 10, (20, 3)):
+        paper = [sig * (x[1] - x[0]), -x[1] - x[0] * x[2], -b * x[2] + x[0] * x[1] - b * r]
+        for j in range(3):
+            assert o.drift(x, j) == pytest.approx(paper[j], rel=1e-13, abs=1e-11)
+
+
+def test_l96_equilibrium_and_definition(oracle_mod):
+    """(F, ..., F) is an equilibrium of Lorenz '96 (Sec. 5.1.2); components follow the cyclic formula."""
+    cfg = S.l96_6d()
+    o = oracle_mod.Oracle(cfg)
+    for j in range(6):
+        assert o.drift([4.0] * 6, j) == 0.0
+    x = np.array([1.0, -2.0, 3.0, 0.5, -1.5, 2.5])
+    for j in range(6):
+        want = (x[(j + 1) % 6] - x[(j - 2) % 6]) * x[(j - 1) % 6] - x[j] + 4.0
+        assert o.drift(x, j) == pytest.approx(want, rel=1e-15)
+
+
+def test_face_velocity_is_drift_at_backward_face_centre(oracle_mod):
+    """f_{i-1/2 e_j, j} is f_j at mean + i h with coordinate j moved back by h_j / 2 (Eq. 7)."""
+    cfg = S.l63_small()
+    o = oracle_mod.Oracle(cfg)
+    rng = np.random.default_rng(1)
+    for i in rng.integers(-20, 20, (30, 3)):
+        for j in range(3):
+            assert o.face_vel(i, j) == pytest.approx(float(_ref.face_velocity(cfg, i[None, :], j)[0]), rel=1e-14, abs=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Initial condition
+# ---------------------------------------------------------------------------
+
+def _lattice_count(cfg):
+    n = cfg["n"]
+    R2 = 2 * math.log(1 / cfg["thresh_rel"])
+    cov = np.asarray(cfg["cov"])
+    r = [math.ceil(math.sqrt(R2 * cov[j, j]) / cfg["h"][j]) for j in range(n)]
+    g = np.stack(np.meshgrid(*[np.arange(-rj, rj + 1) for rj in r], indexing="ij"), -1).reshape(-1, n)
+    y = g * np.asarray(cfg["h"])
+    q = np.einsum("ij,jk,ik->i", y, np.linalg.inv(cov), y)
+    return g[q <= R2], q[q <= R2]
+
+
+@pytest.mark.parametrize("name,expected", [("l63_small", 3743), ("l63_corrections", 110195)])
+def test_init_lattice_count(oracle_mod, name, expected):
+    """The initial grid is exactly the lattice points of the ellipsoid (brute-force count)."""
+    cfg = S.workload(name, measurements=[])
+    pts, _ = _lattice_count(cfg)
+    assert len(pts) == expected
+    o = oracle_mod.Oracle(cfg).init_gaussian()
+    assert o.count() == expected
+
+
+def test_init_density_is_normalised_gaussian(oracle_mod):
+    cfg = S.l63_small()
+    o = oracle_mod.Oracle(cfg).init_gaussian()
+    idx, p = o.export()
+    pts, q = _lattice_count(cfg)
+    order = np.lexsort(pts.T[::-1])
+    pts, q = pts[order], q[order]
+    assert np.array_equal(idx, pts)
+    want = np.exp(-q / 2)
+    want /= 0.125 * want.sum()
+    assert np.max(np.abs(p - want)) <= 1e-14 * want.max()
+    assert 0.125 * p.sum() == pytest.approx(1.0, abs=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# CTU arithmetic: closed forms for constant velocity (Eq. 7 + Algorithm 1)
+# ---------------------------------------------------------------------------
+
+def _binom_pmf(N, a):
+    a = Fraction(a)
+    return [math.comb(N, k) * a ** k * (1 - a) ** (N - k) for k in range(N + 1)]
+
+
+# Grow mode 1 (every axis and pairwise-edge neighbour of a non-zero cell) makes the sparse
+# grid hold every cell the dense-box scheme touches, so the dense closed forms apply for
+# every sign.  Under directional growth Algorithm 1 never visits the wave at the forward
+# face of an upwind-frontier cell (its owner cell is not in the grid), so the closed form
+# holds there only when all velocities are positive (no flow enters through the frontier).
+SIGN_CASES_2D = [(s, 1) for s in itertools.product([1, -1], repeat=2)] + [((1, 1), 0)]
+
+
+@pytest.mark.parametrize("signs,grow_mode", SIGN_CASES_2D)
+@pytest.mark.parametrize("a,b", [(0.5, 0.5), (0.25, 0.75), (0.375, 0.125)])
+def test_ctu_2d_constant_velocity_is_tensor_product_of_upwind_steps(oracle_mod, signs, grow_mode, a, b):
+    """In 2-D with constant velocity, DCU + Algorithm 1 is the product of the two 1-D upwind
+    steps, so a unit mass after N steps is Binom(N, a) x Binom(N, b) exactly (dyadic a, b)."""
+    dt, h = 0.5, [1.0, 0.25]  # anisotropic cells: Courant numbers a = |u_1| dt / h_1, b = |u_2| dt / h_2
+    u = [signs[0] * a * h[0] / dt, signs[1] * b * h[1] / dt]
+    cfg = S.uniform_config(2, u, h=h, dt_fixed=dt, prune_every=0, limiter=0, grow_mode=grow_mode)
+    o = oracle_mod.Oracle(cfg).init_cells([[0, 0]], [1.0])
+    N = 8
+    o.step(N * dt)
+    assert o.stats()["steps"] == N
+    idx, p = o.export()
+    pa, pb = _binom_pmf(N, a), _binom_pmf(N, b)
+    got = {tuple(i): v for i, v in zip(idx, p)}
+    for k1 in range(N + 1):
+        for k2 in range(N + 1):
+            want = float(pa[k1] * pb[k2])
+            assert got.get((signs[0] * k1, signs[1] * k2), 0.0) == want
+    assert sum(abs(v) for v in p) == pytest.approx(1.0, abs=1e-15)
+
+
+@pytest.mark.parametrize("signs,grow_mode", [(s, 1) for s in itertools.product([1, -1], repeat=3)]
+                         + [((1, 1, 1), 0)])
+def test_ctu_3d_constant_velocity_is_pairwise_operator(oracle_mod, signs, grow_mode):
+    """In n-D the one-step CTU operator is 1 - sum a_j D_j + sum_{j<l} a_j a_l D_j D_l (no
+    triple products): pairwise corner transport only.  Checked against a dense convolution."""
+    dt, a, h = 0.5, [0.25, 0.125, 0.375], [0.5, 1.0, 2.0]
+    u = [s * ai * hi / dt for s, ai, hi in zip(signs, a, h)]
+    cfg = S.uniform_config(3, u, h=h, dt_fixed=dt, prune_every=0, limiter=0, grow_mode=grow_mode)
+    idx, p = S.random_blob(3, 1, seed=7)
+    o = oracle_mod.Oracle(cfg).init_cells(idx, p)
+    lo, shape = [-9] * 3, [19] * 3
+    D = _ref.to_dense(idx, p, lo, shape)
+    for _ in range(5):
+        D = _ref.pairwise_operator_step(D, a, signs)
+    o.step(5 * dt)
+    oi, op = o.export()
+    assert np.max(np.abs(_ref.to_dense(oi, op, lo, shape) - D)) <= 8 * EPS * np.abs(D).max()
+
+
+@pytest.mark.parametrize("n,axis,limiter", [(1, 0, 0), (1, 0, 1), (2, 1, 1), (3, 2, 0), (3, 0, 1)])
+@pytest.mark.parametrize("sign", [1, -1])
+def test_translation_at_courant_one(oracle_mod, n, axis, limiter, sign):
+    """Uniform drift along one axis with C = 1 moves every cell exactly one cell per step, for
+    either limiter (the high-resolution factor 1 - C vanishes)."""
+    u = [0.0] * n
+    u[axis] = 2.0 * sign
+    cfg = S.uniform_config(n, u, h=0.5, cfl=1.0, prune_every=0, limiter=limiter)
+    rng = np.random.default_rng(3)
+    idx, _ = S.random_blob(n, 2, seed=11)
+    p = rng.integers(1, 1000, len(idx)) / 1024.0  # dyadic values: the update sums are exact
+    o = oracle_mod.Oracle(cfg).init_cells(idx, p)
+    for k in range(1, 4):
+        _step1(o)
+        assert o.stats()["dt_last"] == 0.25
+        oi, op = o.export()
+        got = {tuple(i): v for i, v in zip(oi, op)}
+        shifted = idx.copy()
+        shifted[:, axis] += sign * k
+        want = {tuple(i): v for i, v in zip(shifted, p)}
+        for key, v in want.items():
+            assert got.get(key, 0.0) == v
+        assert all(v == 0.0 for key, v in got.items() if key not in want)
+
+
+def test_first_order_moments_1d(oracle_mod):
+    """1-D upwind with constant velocity convolves the density with Bernoulli(a): the mean
+    moves by u dt and the variance grows by h^2 a (1 - a) every step."""
+    h, u, dt = 0.5, 1.5, 0.1
+    a = u * dt / h
+    cfg = S.uniform_config(1, [u], h=h, dt_fixed=dt, prune_every=0, limiter=0)
+    idx, p = S.random_blob(1, 6, seed=4)
+    o = oracle_mod.Oracle(cfg).init_cells(idx, p)
+    m0, c0 = _ref.grid_moments(cfg, idx, p)
+    for k in range(1, 11):
+        _step1(o)
+        oi, op = o.export()
+        m, c = _ref.grid_moments(cfg, oi, op)
+        assert m[0] == pytest.approx(m0[0] + k * u * dt, abs=1e-12)
+        assert c[0, 0] == pytest.approx(c0[0, 0] + k * h * h * a * (1 - a), abs=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# High-resolution term (reading R3)
+# ---------------------------------------------------------------------------
+
+def test_mc_limiter_is_tvd_and_adds_no_extrema(oracle_mod):
+    """With uniform 1-D drift and C <= 1 the MC-limited scheme is total-variation diminishing."""
+    cfg = S.uniform_config(1, [1.0], h=1.0, cfl=0.8, prune_every=0, limiter=1)
+    rng = np.random.default_rng(5)
+    idx = np.arange(-15, 15)[:, None]
+    p = np.where(np.abs(idx[:, 0]) < 6, 1.0, 0.0) + 0.3 * rng.random(len(idx)) * (np.abs(idx[:, 0]) < 10)
+    o = oracle_mod.Oracle(cfg).init_cells(idx, p)
+
+    def tv(q):
+        return np.sum(np.abs(np.diff(np.concatenate([[0.0], q, [0.0]]))))
+
+    prev_tv, lo, hi = tv(p), p.min(), p.max()
+    for _ in range(30):
+        _step1(o)
+        _, q = o.export()
+        assert tv(q) <= prev_tv + 1e-13
+        assert q.max() <= hi + 1e-13 and q.min() >= min(lo, 0.0) - 1e-13
+        prev_tv = tv(q)
+
+
+def _advect_error(oracle_mod, h, limiter):
+    u, T = 1.0, 1.0
+    cfg = S.uniform_config(1, [u], h=h, cfl=0.5, prune_every=0, limiter=limiter)
+    i = np.arange(int(-4 / h), int(4 / h) + 1)
+    x = i * h
+    p = np.exp(-x ** 2 / (2 * 0.5 ** 2))
+    o = oracle_mod.Oracle(cfg).init_cells(i[:, None], p)
+    o.step(T)
+    oi, op = o.export()
+    xe = oi[:, 0] * h
+    return h * np.sum(np.abs(op - np.exp(-(xe - u * T) ** 2 / (2 * 0.5 ** 2))))
+
+
+def test_mc_term_gives_second_order_convergence(oracle_mod):
+    """Halving h cuts the L1 error ~4x with the MC term and ~2x without it (smooth profile)."""
+    e_hr = [_advect_error(oracle_mod, h, 1) for h in (0.1, 0.05, 0.025)]
+    e_lo = [_advect_error(oracle_mod, h, 0) for h in (0.1, 0.05, 0.025)]
+    assert e_hr[0] / e_hr[1] > 3.0 and e_hr[1] / e_hr[2] > 3.0
+    assert 1.6 < e_lo[0] / e_lo[1] < 2.4 and 1.6 < e_lo[1] / e_lo[2] < 2.4
+    assert e_hr[2] < e_lo[2] / 5
+
+
+# ---------------------------------------------------------------------------
+# Variable velocity: sparse machinery vs an independent dense-box formulation
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,limiter,seed", [(1, 1, 1), (2, 0, 2), (2, 1, 3), (3, 0, 4), (3, 1, 5), (4, 1, 6)])
+def test_sparse_grid_equals_dense_box(oracle_mod, n, limiter, seed):
+    """With every edge neighbour grown, no threshold and no prune, the sparse oracle equals
+    the CTU step on a dense box (computed here in gather form) for a variable drift."""
+    ab = S.random_linear(n, seed=seed, scale=0.5)
+    dt = 0.05
+    h = [0.5, 0.25, 0.4, 0.3][:n]  # anisotropic cells
+    cfg = S.linear_config(n, ab, h=h, dt_fixed=dt, prune_every=0, limiter=limiter, grow_mode=1)
+    idx, p = S.random_blob(n, 2 if n < 4 else 1, seed=seed)
+    o = oracle_mod.Oracle(cfg).init_cells(idx, p)
+    steps = 6 if n < 4 else 3
+    lo, shape = [-(steps + 5)] * n, [2 * (steps + 5) + 1] * n
+    D = _ref.to_dense(idx, p, lo, shape)
+    for _ in range(steps):
+        D = _ref.dense_ctu_step(cfg, D, lo, dt, limiter)
+    o.step(steps * dt)
+    oi, op = o.export()
+    assert np.max(np.abs(_ref.to_dense(oi, op, lo, shape) - D)) <= 1e-14 * np.abs(D).max()
+
+
+# ---------------------------------------------------------------------------
+# Conservation (reading R1)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("which", ["l63", "l96", "linear3"])
+@pytest.mark.parametrize("limiter", [0, 1])
+def test_mass_conserved_without_prune(oracle_mod, which, limiter):
+    """With prune off the update conserves sum P to rounding every step, for any drift."""
+    if which == "l63":
+        cfg = S.with_(S.l63_small(), prune_every=0, limiter=limiter, thresh_rel=1e-3)
+    elif which == "l96":
+        cfg = S.with_(S.l96_6d(h=0.6, thresh_rel=1e-2), prune_every=0, limiter=limiter)
+    else:
+        cfg = S.linear_config(3, S.random_linear(3, 9, scale=2.0), h=0.25, prune_every=0, limiter=limiter,
+                              thresh_rel=1e-4, cov=(0.3 * np.eye(3)).tolist())
+    o = oracle_mod.Oracle(cfg).init_gaussian()
+    m_prev = o.stats()["mass"]
+    for _ in range(12):
+        _step1(o)
+        st = o.stats()
+        assert abs(st["mass"] - m_prev) <= 4 * st["cells"] * EPS * m_prev
+        m_prev = st["mass"]
+
+
+def test_prune_renormalises(oracle_mod):
+    cfg = S.with_(S.l63_small(), prune_every=5)
+    o = oracle_mod.Oracle(cfg).init_gaussian()
+    o.step(1.0, 5)
+    st = o.stats()
+    assert st["prunes"] == 1
+    assert st["mass"] == pytest.approx(1.0, abs=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# CFL step (Eq. 8, reading R2) and stop-time clamping
+# ---------------------------------------------------------------------------
+
+def test_cfl_step_and_exact_stop(oracle_mod):
+    cfg = S.l63_small()
+    o = oracle_mod.Oracle(cfg).init_gaussian()
+    o.grow()
+    idx, _ = o.export()
+    s = np.zeros(len(idx))
+    for j in range(3):
+        s = s + np.abs(_ref.face_velocity(cfg, idx, j)) / cfg["h"][j]
+    assert o.smax() == pytest.approx(s.max(), rel=1e-14)
+    o2 = oracle_mod.Oracle(cfg).init_gaussian()
+    _step1(o2)
+    assert o2.log()[0][1] == pytest.approx(0.9 / s.max(), rel=1e-14)
+    o2.step(0.0123)
+    assert o2.stats()["t"] == 0.0123
+
+
+# ---------------------------------------------------------------------------
+# Directional grow and prune (Sec. 3.3, reading R4): brute force over all 3^n - 1 neighbours
+# ---------------------------------------------------------------------------
+
+def _downwind_ok(cfg, c, d):
+    """Offset d (entries in {-1,0,1}, at most two non-zero) is downwind of cell c."""
+    if not 1 <= np.count_nonzero(d) <= 2:
+        return False
+    for j, s in enumerate(d):
+        if s == 1 and not float(_ref.face_velocity(cfg, (c + np.eye(len(c), dtype=int)[j])[None], j)[0]) > 0:
+            return False
+        if s == -1 and not float(_ref.face_velocity(cfg, c[None], j)[0]) < 0:
+            return False
+    return True
+
+
+def test_grow_set_brute_force(oracle_mod):
+    cfg = S.with_(S.l63_small(), thresh_rel=1e-2)
+    o = oracle_mod.Oracle(cfg).init_gaussian()
+    idx, p = o.export()
+    pstar = cfg["thresh_rel"] * p.max()
+    want = set(map(tuple, idx))
+    offsets = [np.array(d) for d in itertools.product([-1, 0, 1], repeat=3)]
+    for c, v in zip(idx, p):
+        if v >= pstar:
+            for d in offsets:
+                if _downwind_ok(cfg, c, d):
+                    want.add(tuple(c + d))
+    o.grow()
+    gi, gp = o.export()
+    assert set(map(tuple, gi)) == want
+    assert len(want) > len(idx)
+    new = [tuple(i) for i in gi if tuple(i) not in set(map(tuple, idx))]
+    got = {tuple(i): v for i, v in zip(gi, gp)}
+    assert all(got[k] == 0.0 for k in new)
+
+
+def test_prune_set_brute_force(oracle_mod):
+    cfg = S.with_(S.l63_small(), thresh_rel=1e-2)
+    o = oracle_mod.Oracle(cfg).init_gaussian()
+    o.grow()
+    o.step(1.0, 3)
+    idx, p = o.export()
+    cells = {tuple(i): v for i, v in zip(idx, p)}
+    pstar = cfg["thresh_rel"] * p.max()
+    offsets = [np.array(d) for d in itertools.product([-1, 0, 1], repeat=3)]
+    keep = set()
+    for c, v in zip(idx, p):
+        if v >= pstar:
+            keep.add(tuple(c))
+            continue
+        for d in offsets:
+            # upwind neighbour u = c + d: the flow goes from u into c, i.e. c - u is downwind of u
+            u = c + d
+            if tuple(u) in cells and cells[tuple(u)] >= pstar and _upwind_ok(cfg, c, d):
+                keep.add(tuple(c))
+                break
+    o.prune()
+    gi, gp = o.export()
+    assert set(map(tuple, gi)) == keep
+    assert len(keep) < len(idx)
+    assert 0.125 * gp.sum() == pytest.approx(1.0, abs=1e-14)
+
+
+def _upwind_ok(cfg, c, d):
+    """Offset d points from c to an upwind neighbour: +1 if f at c's forward face < 0,
+    -1 if f at c's backward face > 0, at most two non-zero entries."""
+    if not 1 <= np.count_nonzero(d) <= 2:
+        return False
+    for j, s in enumerate(d):
+        if s == 1 and not float(_ref.face_velocity(cfg, (c + np.eye(len(c), dtype=int)[j])[None], j)[0]) < 0:
+            return False
+        if s == -1 and not float(_ref.face_velocity(cfg, c[None], j)[0]) > 0:
+            return False
+    return True
+
+
+# ---------------------------------------------------------------------------
+# Bayesian correction (Eq. 4): Gaussian prior x Gaussian likelihood = Kalman update
+# ---------------------------------------------------------------------------
+
+def _kalman(mean, cov, comp, y, sigma):
+    s = cov[comp, comp] + sigma * sigma
+    K = cov[:, comp] / s
+    return mean + K * (y - mean[comp]), cov - np.outer(K, cov[comp, :])
+
+
+@pytest.mark.parametrize("comp", [0, 2])
+def test_correction_is_kalman_update(oracle_mod, comp):
+    cov = np.array([[1.0, 0.3, 0.1], [0.3, 0.8, -0.2], [0.1, -0.2, 0.6]])
+    cfg = S.linear_config(3, [0.0] * 12, h=0.2, thresh_rel=1e-12, cov=cov.tolist(), prune_every=0,
+                          mean=[1.0, -2.0, 0.5])
+    o = oracle_mod.Oracle(cfg).init_gaussian()
+    idx, p = o.export()
+    m0, c0 = _ref.grid_moments(cfg, idx, p)
+    assert np.allclose(m0, cfg["mean"], atol=1e-9) and np.allclose(c0, cov, atol=1e-8)
+    y, sigma = 1.3, 0.7
+    o.correct(comp, y, sigma)
+    idx, p = o.export()
+    m1, c1 = _ref.grid_moments(cfg, idx, p)
+    mk, ck = _kalman(np.array(cfg["mean"]), cov, comp, y, sigma)
+    assert np.allclose(m1, mk, atol=1e-8) and np.allclose(c1, ck, atol=1e-7)
+    assert o.stats()["mass"] == pytest.approx(1.0, abs=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# Linear flow: grid moments converge to the exact Gaussian solution as h -> 0
+# ---------------------------------------------------------------------------
+
+def test_linear_flow_moments_converge(oracle_mod):
+    A = np.array([[-0.5, 1.0], [-1.0, -0.3]])
+    b = np.array([0.4, -0.2])
+    mean0, cov0, T = np.array([0.5, -0.5]), np.array([[0.3, 0.05], [0.05, 0.2]]), 0.3
+    E = scipy.linalg.expm(A * T)
+    m_ex = E @ mean0 + np.linalg.solve(A, (E - np.eye(2)) @ b)
+    c_ex = E @ cov0 @ E.T
+    errs = []
+    for h in (0.2, 0.1, 0.05):
+        cfg = S.linear_config(2, list(A.reshape(-1)) + list(b), h=h, thresh_rel=1e-10, cov=cov0.tolist(),
+                              mean=list(mean0), prune_every=10, limiter=1)
+        o = oracle_mod.Oracle(cfg).init_gaussian()
+        o.step(T)
+        idx, p = o.export()
+        m, c = _ref.grid_moments(cfg, idx, p)
+        errs.append(np.abs(m - m_ex).max() + np.abs(c - c_ex).max())
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 2e-3
+
+
+# ---------------------------------------------------------------------------
+# Marginals (Sec. 5.1.2)
+# ---------------------------------------------------------------------------
+
+def test_marginals_brute_force_and_gaussian(oracle_mod):
+    cov = np.diag([0.3, 0.5, 0.4, 0.6])
+    cfg = S.linear_config(4, [0.0] * 20, h=0.25, thresh_rel=1e-8, cov=cov.tolist(), prune_every=0,
+                          mean=[0.0, 1.0, -1.0, 0.5])
+    o = oracle_mod.Oracle(cfg).init_gaussian()
+    idx, p = o.export()
+    mi, mv = o.marginals([1, 3])
+    groups = {}
+    for i, v in zip(idx, p):
+        k = (i[1], i[3])
+        groups[k] = groups.get(k, 0.0) + v
+    assert len(groups) == len(mi)
+    for k, v in zip(mi, mv):
+        assert v == pytest.approx(groups[tuple(k)] * 0.25 * 0.25, rel=1e-13)
+    assert mv.sum() * 0.25 * 0.25 == pytest.approx(1.0, abs=1e-12)
+    sub = S.linear_config(2, [0.0] * 6, h=0.25, mean=[1.0, 0.5])
+    m, c = _ref.grid_moments(sub, mi, mv)
+    assert np.allclose(m, [1.0, 0.5], atol=1e-6) and np.allclose(c, np.diag([0.5, 0.6]), atol=1e-5)
