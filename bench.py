@@ -1,0 +1,191 @@
+"""Benchmark of the GBEES hot path on one MI355X.
+
+One benchmark step is one whole propagation job of the Lorenz '96 6D workload
+(n = 6, F = 4, mean (4.5, 4, ..., 4), cov 0.25 I, h = 0.25, thr 1e-7, CFL 0.9,
+MC-limited CTU, prune every 20 steps, t in [0, 1] with one x1 correction at
+t = 0.5): Gaussian initialisation, grow / CFL / flux / update every step,
+prune + renormalisation, the Bayesian correction.  The metric is CTU
+cell-updates per second over the whole job (the paper's "cells/s").
+
+Prints one JSON line (metric, value, roofline of the dominant kernel measured
+with HIP events on the launch stream, and the CPU oracle on a bounded sample).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
+
+
+def flux_b_bytes_per_brick(n, real_size):
+    """Algorithmic bytes of one brick (64 cell slots) in the flux-B pass: density
+    read, n corrected states read, updated density written, brick key, mask and
+    2n axis-neighbour indices.  Neighbour values count zero (perfect reuse)."""
+    return 64 * real_size + 64 * n * real_size + 64 * real_size + 8 + 8 + 4 * 2 * n
+
+
+def flux_a_bytes_per_brick(n, real_size):
+    """Flux-A pass: density read, n corrected states written, key, mask, links."""
+    return 64 * real_size + 64 * n * real_size + 8 + 8 + 4 * 2 * n
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("gbees_dev.hpp", "kernels.hip"):
+        with open(os.path.join(ROOT, "paper_2508_13986_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, bricks_per_launch):
+    """HBM bytes per flux-B launch from committed rocprofv3 counter runs, if they
+    were taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"flux_b_{workload}_pmc.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    per_brick = (d["fetch_bytes_per_launch"] + d["write_bytes_per_launch"]) / d["bricks_per_launch"]
+    return per_brick * bricks_per_launch
+
+
+def run_job(G, cfg, max_cells, profile):
+    grid = G.Grid.gaussian(cfg, max_cells)
+    if profile:
+        grid.profile(True)
+    G.run_scenario(cfg, grid=grid)
+    st = grid.stats()
+    prof = grid.profile_read() if profile else None
+    grid.close()
+    return st, prof
+
+
+def cpu_baseline(budget_s):
+    """The oracle, single-threaded, on the downsampled L96 6D grid (h = 0.5, thr
+    1e-5): as many whole steps as fit in the time budget."""
+    import oracle
+    from paper_2508_13986_amd import scenarios as S
+
+    cfg = S.l96_6d_downsampled()
+    o = oracle.Oracle(cfg).init_gaussian()
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        o.step(cfg["t_end"], 1)
+    dt = time.perf_counter() - t0
+    st = o.stats()
+    return {"value": st["cell_updates"] / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"L96 6D h=0.5 thr=1e-5 ({o.count()} cells), first {st['steps']} steps, "
+                      f"{dt:.1f} s single-threaded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="l96_6d")
+    ap.add_argument("--max-cells", type=int, default=64 * 4_000_000)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (see the design notes on sharding)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2508_13986_amd import gbees as G
+    from paper_2508_13986_amd import scenarios as S
+
+    torch.cuda.set_device(0)
+    cfg = S.workload(args.workload)
+    n = cfg["n"]
+    real_size = 4 if cfg.get("precision", 0) == 1 else 8
+
+    for _ in range(args.warmup):
+        run_job(G, cfg, args.max_cells, profile=False)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    totals = {"cell_updates": 0, "brick_updates": 0, "steps": 0}
+    prof_sum = {}
+    last = None
+    for _ in range(args.steps):
+        st, prof = run_job(G, cfg, args.max_cells, profile=True)
+        for k in totals:
+            totals[k] += st[k]
+        for k, (ms, cnt) in prof.items():
+            a = prof_sum.setdefault(k, [0.0, 0])
+            a[0] += ms
+            a[1] += cnt
+        last = st
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    value = totals["cell_updates"] / elapsed
+    fb_ms, fb_n = prof_sum["flux_b"]
+    fa_ms, fa_n = prof_sum["flux_a"]
+    bricks_per_launch = totals["brick_updates"] / max(fb_n, 1)
+    avg_b = fb_ms / 1e3 / max(fb_n, 1)
+    avg_a = fa_ms / 1e3 / max(fa_n, 1)
+    bytes_b = flux_b_bytes_per_brick(n, real_size) * bricks_per_launch
+    bytes_a = flux_a_bytes_per_brick(n, real_size) * bricks_per_launch
+    achieved = bytes_b / avg_b / 1e9
+    traffic = measured_traffic(args.workload, bricks_per_launch)
+    cells_per_step = totals["cell_updates"] / max(totals["steps"], 1)
+    line = {
+        "metric": "CTU cell-updates/s (Lorenz-96 6D)",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if real_size == 4 else "f64",
+        "data": "synthetic (seeded Gaussian initial pdf and seeded truth-trajectory measurement)",
+        "config": {
+            "workload": f"{args.workload}: Lorenz-96 n={n} F=4, h={cfg['h'][0]}, thr={cfg['thresh_rel']}, "
+                        f"CFL {cfg['cfl']}, MC limiter, prune every {cfg['prune_every']}, t in [0,{cfg['t_end']}], "
+                        f"{len(cfg['measurements'])} correction(s)",
+            "steps_per_job": totals["steps"] // args.steps,
+            "cells_per_step_mean": cells_per_step,
+            "cells_final": last["cells"],
+            "bricks_per_step_mean": bricks_per_launch,
+            "brick_occupancy": cells_per_step / (64 * bricks_per_launch),
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_flux_b",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS,
+            "traffic": traffic,
+            "avg_launch_us": avg_b * 1e6,
+            "algorithmic_bytes_per_launch": bytes_b,
+        },
+        "phases_ms_per_job": {k: v[0] / args.steps for k, v in prof_sum.items()},
+        "flux_passes_cell_updates_per_s": cells_per_step / (avg_a + avg_b),
+        "flux_a_gbps": bytes_a / avg_a / 1e9,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args.cpu_budget)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

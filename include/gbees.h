@@ -1,0 +1,154 @@
+/*
+ * gbees.h -- C ABI of the GBEES hot path on MI355X (gfx950).
+ *
+ * GBEES (Grid-based Bayesian Estimation Exploiting Sparsity, GBEES-GPU,
+ * arXiv 2508.13986) propagates a probability density p(x, t), x in R^n, on a
+ * sparse grid of control volumes (Sec. 2.1, Eq. 5) with the conservative
+ * advection equation (Sec. 2, Eq. 3), and corrects it with Bayes' rule at
+ * measurement times (Eq. 4).  One time step is: grow the grid downwind of the
+ * cells above the probability threshold (Sec. 3.3), take the CFL time step
+ * (Sec. 3.2, Eq. 8), compute Donor Cell Upwind fluxes (Eq. 7) with Corner
+ * Transport Upwind corrections (Algorithm 1) and an optional high-resolution
+ * term, update the densities, and every few steps prune cells below the
+ * threshold that have no upwind neighbour above it (Algorithm 3), then
+ * renormalise.
+ *
+ * Conventions of every entry point:
+ *  - Return 0 (GBEES_OK) or a negative GBEES_E_* code (gbees_strerror names it).
+ *  - Memory: the caller owns the arena, a device buffer of at least
+ *    gbees_arena_bytes(cfg) bytes that must outlive the context; the library
+ *    allocates no device memory.  Host buffers belong to the caller.
+ *  - Streams: all device work is enqueued on the caller's HIP stream (passed
+ *    as void*, may be NULL for the null stream).  Calls that return host data
+ *    synchronise that stream.
+ *  - Cell indices: cell i in Z^n has centre mean + i*h (mean and h from the
+ *    config); index arrays are row-major [count][n] int32.
+ *  - Densities are cell averages normalised so that prod(h) * sum P = 1.
+ *  - Exported cells are sorted lexicographically by index.
+ *  - After GBEES_E_CAPACITY or GBEES_E_RANGE the context is unusable except
+ *    for gbees_get_stats and gbees_destroy (every other call returns the error).
+ *  - Not thread-safe per context; distinct contexts are independent.
+ */
+#ifndef GBEES_H
+#define GBEES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  GBEES_OK = 0,
+  GBEES_E_ARG = -1,      /* invalid argument or configuration */
+  GBEES_E_CAPACITY = -2, /* the grid outgrew max_cells (or the hashtable) */
+  GBEES_E_RANGE = -3,    /* a cell index left the packable coordinate range */
+  GBEES_E_DEVICE = -4,   /* a HIP runtime call failed */
+  GBEES_E_BUFFER = -5,   /* output buffer too small; *count_out holds the size needed */
+  GBEES_E_STATE = -6     /* the context is in an error state */
+};
+
+/* Drift models f(x).  Lorenz '63 and Lorenz '96 are the paper's test systems
+ * (Sec. 5.1.1, 5.1.2); LINEAR (f = A x + b) and UNIFORM (f = b) serve tests. */
+enum { GBEES_L63 = 1, GBEES_L96 = 2, GBEES_LINEAR = 3, GBEES_UNIFORM = 4 };
+
+typedef struct gbees_ctx gbees_ctx;
+
+typedef struct {
+  int32_t n;           /* dimension: 3 for L63, 4..6 for L96, 1..6 for LINEAR/UNIFORM */
+  int32_t model;       /* GBEES_L63 | GBEES_L96 | GBEES_LINEAR | GBEES_UNIFORM */
+  double params[48];   /* L63: sigma, rho, beta, z_shift (f evaluated at x3 + z_shift);
+                          L96: F; LINEAR: A (n*n, row-major) then b (n); UNIFORM: b (n) */
+  double h[6];         /* cell widths h_j > 0 (Eq. 5) */
+  double mean[6];      /* initial mean; also the centre of cell 0 */
+  double cov[36];      /* initial covariance, n*n row-major, symmetric positive definite */
+  double thresh_rel;   /* p* = thresh_rel * max P; 0 = grow from every non-zero cell, never prune */
+  double cfl;          /* Courant number C in (0, 1]: dt = C / max_i sum_j |f_j| / h_j */
+  double dt_fixed;     /* > 0 replaces the CFL step (tests) */
+  int32_t prune_every; /* prune after every prune_every-th step; 0 = never */
+  int32_t limiter;     /* 0: Eq. 7 + Algorithm 1 only; 1: plus the MC-limited high-resolution term */
+  int32_t grow_mode;   /* 0: downwind axis and pairwise-edge neighbours; 1: every one of them */
+  int32_t precision;   /* 0: FP64 densities; 1: FP32 densities and fluxes, FP64 reductions */
+  int64_t max_cells;   /* capacity in cell slots (cells are stored in bricks of 64) */
+  double hash_load;    /* hashtable load bound (Sec. 4.2), 0 => 0.5 */
+} gbees_config;
+
+typedef struct {
+  double t;              /* current time */
+  double dt_last;        /* last time step */
+  double mass;           /* prod(h) * sum P after the last reduction */
+  double max_p;          /* max P of the current grid */
+  double smax;           /* max_i sum_j |f_{i-1/2 e_j, j}| / h_j over the grid */
+  int64_t steps;         /* time steps taken since initialisation */
+  int64_t cell_updates;  /* sum over steps of the number of cells updated */
+  int64_t brick_updates; /* sum over steps of the number of bricks swept by the flux passes */
+  int64_t cells;         /* cells in the grid */
+  int64_t bricks;        /* bricks in use */
+  int64_t prunes;        /* prune passes run */
+} gbees_stats;
+
+/* Device bytes the arena must hold for cfg (0 if cfg is invalid). */
+size_t gbees_arena_bytes(const gbees_config* cfg);
+
+/* Initial condition (Sec. 5.1: a Gaussian pdf): the grid is every cell i whose
+ * centre offset y = i*h satisfies y' cov^-1 y <= 2 ln(1/thresh_rel), with
+ * P = exp(-y' cov^-1 y / 2), normalised.  Requires 0 < thresh_rel < 1.
+ * On success *out owns nothing but host bookkeeping; the grid lives in arena. */
+int gbees_init_gaussian(const gbees_config* cfg, void* arena, size_t arena_bytes, void* hip_stream,
+                        gbees_ctx** out);
+
+/* Initial condition from caller cells: count cells with indices idx[count][n]
+ * (distinct) and densities P[count] (used as given, not normalised), at time t0. */
+int gbees_init_cells(const gbees_config* cfg, const int32_t* idx, const double* P, int64_t count, double t0,
+                     void* arena, size_t arena_bytes, void* hip_stream, gbees_ctx** out);
+
+/* Advance until t == t_stop exactly (the last step is clamped, Sec. 3.2), or
+ * until max_steps (> 0) steps were taken.  Each step: grow, CFL step, DCU +
+ * CTU fluxes (+ high-resolution term), update; prune + renormalise after every
+ * prune_every-th step.  Fills *out (may be NULL). */
+int gbees_step(gbees_ctx* ctx, double t_stop, int64_t max_steps, gbees_stats* out);
+
+/* Bayesian correction (Eq. 4) with measurement y = x_component + noise,
+ * noise ~ N(0, sigma^2): P_i *= exp(-(y - x_i,component)^2 / (2 sigma^2)) at
+ * the cell centres, then prune (if pruning is enabled) and renormalise. */
+int gbees_correct(gbees_ctx* ctx, int32_t component, double y, double sigma);
+
+/* Marginal over the dimensions in dim_mask (bit j = keep x_j; Sec. 5.1.2):
+ * M(k) = sum over cells i with i restricted to the mask equal to k of
+ * P_i * prod_{j not in mask} h_j.  Writes count rows, sorted by k, into
+ * idx_out[count][popcount(mask)] and val_out[count]; GBEES_E_BUFFER (with
+ * *count_out set) if capacity < count. */
+int gbees_marginals(gbees_ctx* ctx, uint32_t dim_mask, int64_t capacity, int32_t* idx_out, double* val_out,
+                    int64_t* count_out);
+
+/* Copy the grid out: idx[count][n], P[count] sorted by index, and the time.
+ * GBEES_E_BUFFER (with *count set) if capacity < count.  t may be NULL. */
+int gbees_export(gbees_ctx* ctx, int64_t capacity, int32_t* idx, double* P, int64_t* count, double* t);
+
+/* Current statistics (synchronises the stream). */
+int gbees_get_stats(gbees_ctx* ctx, gbees_stats* out);
+
+/* Hashtable probe lengths (Sec. 4.2): mean probes of a successful lookup of
+ * every brick key, of an unsuccessful lookup of n_miss keys that are not in
+ * the table, and the load factor. */
+int gbees_probe_stats(gbees_ctx* ctx, int64_t n_miss, double* mean_hit, double* mean_miss, double* load);
+
+/* Per-pass device time: when enabled, every launch of the grow, flux-A
+ * (transverse-corrected states), flux-B (fluxes + update) and prune passes is
+ * bracketed by HIP events on the context stream; gbees_profile_read returns
+ * accumulated milliseconds and launch counts in the order grow, grow-fix,
+ * flux-A, flux-B, prune, other (6 entries each) and resets them. */
+int gbees_profile(gbees_ctx* ctx, int enable);
+int gbees_profile_read(gbees_ctx* ctx, double* ms, int64_t* launches);
+
+/* Release host bookkeeping (the arena stays the caller's). */
+int gbees_destroy(gbees_ctx* ctx);
+
+const char* gbees_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GBEES_H */

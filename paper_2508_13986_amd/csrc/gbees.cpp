@@ -1,0 +1,696 @@
+// C ABI of the GBEES hot path (include/gbees.h): context, arena layout, the
+// step driver, and the marshalling of exports.  All arithmetic of the method
+// runs in the kernels of kernels.hip; host code here only validates inputs,
+// lays out the caller's arena, enqueues launch sequences and copies results.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <unordered_map>
+#include <vector>
+
+#include "gbees.h"
+#include "gbees_host.hpp"
+
+using gbees::Dev;
+using gbees::KernelTable;
+using gbees::Scalars;
+using gbees::u64;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  uint32_t cap_b = 0;
+  u64 hcap = 0;
+  uint32_t ndef = 0;
+  size_t real_size = 8, qbytes = 0;
+  size_t sb = 0, part = 0, dpart = 0, key = 0, mask = 0, done = 0, abv = 0, P0 = 0, P1 = 0;
+  size_t zero_end = 0;
+  size_t hkey = 0, hval = 0;
+  size_t ff_end = 0;
+  size_t nbr = 0, Q = 0, defer = 0;
+  size_t total = 0;
+};
+
+int effective_model(const gbees_config& c) { return c.model == GBEES_UNIFORM ? GBEES_LINEAR : c.model; }
+
+bool valid_config(const gbees_config& c) {
+  if (c.n < 1 || c.n > 6) return false;
+  if (c.model < GBEES_L63 || c.model > GBEES_UNIFORM) return false;
+  if (!gbees::kernel_table(effective_model(c), c.n, c.precision == 1 ? 1 : 0)) return false;
+  for (int j = 0; j < c.n; ++j)
+    if (!(c.h[j] > 0.0) || !std::isfinite(c.h[j]) || !std::isfinite(c.mean[j])) return false;
+  if (!(c.thresh_rel >= 0.0 && c.thresh_rel < 1.0)) return false;
+  if (!(c.dt_fixed > 0.0) && !(c.cfl > 0.0 && c.cfl <= 1.0)) return false;
+  if (c.prune_every < 0 || (c.limiter != 0 && c.limiter != 1) || (c.grow_mode != 0 && c.grow_mode != 1)) return false;
+  if (c.precision != 0 && c.precision != 1) return false;
+  if (c.max_cells < gbees::kLanes) return false;
+  if (c.max_cells / gbees::kLanes > 0xF0000000ll) return false;
+  return true;
+}
+
+bool make_layout(const gbees_config& c, Layout* L) {
+  if (!valid_config(c)) return false;
+  L->cap_b = static_cast<uint32_t>((c.max_cells + gbees::kLanes - 1) / gbees::kLanes);
+  const double load = (c.hash_load > 0.0 && c.hash_load < 1.0) ? c.hash_load : 0.5;
+  u64 want = static_cast<u64>(std::ceil(L->cap_b / load));
+  u64 h = 1;
+  while (h < want) h <<= 1;
+  L->hcap = h;
+  L->ndef = L->cap_b;
+  L->real_size = c.precision == 1 ? 4 : 8;
+  L->qbytes = static_cast<size_t>(L->cap_b) * gbees::kLanes * std::max<size_t>(c.n * L->real_size, 32);
+  const size_t cb = L->cap_b;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  L->sb = take(sizeof(Scalars));
+  L->part = take((gbees::kMaxWG + 1) * sizeof(uint32_t));
+  L->dpart = take(gbees::kMaxWG * gbees::kPartStride * sizeof(double));
+  L->key = take(cb * 8);
+  L->mask = take(cb * 8);
+  L->done = take(cb * 8);
+  L->abv = take(cb * 8);
+  L->P0 = take(cb * gbees::kLanes * L->real_size);
+  L->P1 = take(cb * gbees::kLanes * L->real_size);
+  L->zero_end = o;
+  L->hkey = take(L->hcap * 8);
+  L->hval = take(L->hcap * 4);
+  L->ff_end = o;
+  L->nbr = take(2 * static_cast<size_t>(c.n) * cb * 4);
+  L->Q = take(L->qbytes);
+  L->defer = take(static_cast<size_t>(L->ndef) * 16);
+  L->total = o;
+  return true;
+}
+
+template <typename Real>
+void fill_dev(Dev<Real>& d, const gbees_config& c, const Layout& L, char* base) {
+  std::memset(&d, 0, sizeof(d));
+  d.n = c.n;
+  d.model = effective_model(c);
+  d.limiter = c.limiter;
+  d.grow_mode = c.grow_mode;
+  if (c.model == GBEES_UNIFORM) {
+    // f = b as the linear field with A = 0: 0 * x + ... + b_j == b_j exactly.
+    for (int j = 0; j < c.n; ++j) d.params[c.n * c.n + j] = c.params[j];
+  } else {
+    std::memcpy(d.params, c.params, sizeof(d.params));
+  }
+  double vol = 1.0;
+  for (int j = 0; j < c.n; ++j) {
+    d.h[j] = c.h[j];
+    d.mean[j] = c.mean[j];
+    vol = vol * c.h[j];
+  }
+  d.vol = vol;
+  d.thresh_rel = c.thresh_rel;
+  d.cfl = c.cfl;
+  d.dt_fixed = c.dt_fixed;
+  d.cap_b = L.cap_b;
+  d.ndef_cap = L.ndef;
+  d.hmask = L.hcap - 1;
+  d.sb = reinterpret_cast<Scalars*>(base + L.sb);
+  d.part = reinterpret_cast<uint32_t*>(base + L.part);
+  d.dpart = reinterpret_cast<double*>(base + L.dpart);
+  d.key = reinterpret_cast<u64*>(base + L.key);
+  d.mask = reinterpret_cast<u64*>(base + L.mask);
+  d.done = reinterpret_cast<u64*>(base + L.done);
+  d.abv = reinterpret_cast<u64*>(base + L.abv);
+  d.P0 = reinterpret_cast<Real*>(base + L.P0);
+  d.P1 = reinterpret_cast<Real*>(base + L.P1);
+  d.hkey = reinterpret_cast<u64*>(base + L.hkey);
+  d.hval = reinterpret_cast<uint32_t*>(base + L.hval);
+  d.nbr = reinterpret_cast<uint32_t*>(base + L.nbr);
+  d.Q = reinterpret_cast<Real*>(base + L.Q);
+  d.defer = reinterpret_cast<u64*>(base + L.defer);
+}
+
+// Inverse of a symmetric positive definite matrix by Gauss-Jordan elimination
+// with partial pivoting; false if singular or not positive definite.
+bool spd_inverse(int n, const double* a_in, double* inv) {
+  double a[6][12];
+  for (int r = 0; r < n; ++r)
+    for (int c = 0; c < 2 * n; ++c) a[r][c] = c < n ? a_in[r * n + c] : (c - n == r ? 1.0 : 0.0);
+  for (int r = 0; r < n; ++r)
+    for (int c = 0; c < r; ++c)
+      if (a_in[r * n + c] != a_in[c * n + r]) return false;
+  // positive definiteness via Cholesky pivots
+  double l[6][6] = {};
+  for (int j = 0; j < n; ++j) {
+    double s = a_in[j * n + j];
+    for (int k = 0; k < j; ++k) s -= l[j][k] * l[j][k];
+    if (!(s > 0.0)) return false;
+    l[j][j] = std::sqrt(s);
+    for (int i = j + 1; i < n; ++i) {
+      double t = a_in[i * n + j];
+      for (int k = 0; k < j; ++k) t -= l[i][k] * l[j][k];
+      l[i][j] = t / l[j][j];
+    }
+  }
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (std::fabs(a[r][col]) > std::fabs(a[piv][col])) piv = r;
+    if (a[piv][col] == 0.0) return false;
+    if (piv != col)
+      for (int c = 0; c < 2 * n; ++c) std::swap(a[piv][c], a[col][c]);
+    const double dv = a[col][col];
+    for (int c = 0; c < 2 * n; ++c) a[col][c] = a[col][c] / dv;
+    for (int r = 0; r < n; ++r) {
+      if (r == col) continue;
+      const double f = a[r][col];
+      if (f == 0.0) continue;
+      for (int c = 0; c < 2 * n; ++c) a[r][c] = a[r][c] - f * a[col][c];
+    }
+  }
+  for (int r = 0; r < n; ++r)
+    for (int c = 0; c < n; ++c) inv[r * n + c] = a[r][c + n];
+  return true;
+}
+
+uint32_t grid_for(uint64_t bricks) {
+  uint64_t g = (bricks + 2 * gbees::kWavesPerWG - 1) / (2 * gbees::kWavesPerWG);
+  g = (g + 7) / 8 * 8;
+  return static_cast<uint32_t>(std::min<uint64_t>(std::max<uint64_t>(g, 8), gbees::kMaxWG));
+}
+
+}  // namespace
+
+struct gbees_ctx {
+  gbees_config cfg;
+  Layout L;
+  char* base = nullptr;
+  hipStream_t stream = nullptr;
+  const KernelTable* kt = nullptr;
+  Dev<double> d64;
+  Dev<float> d32;
+  const void* dev = nullptr;
+  Scalars hsb;
+  int status = GBEES_OK;
+  uint32_t nb_est = 64;
+  int64_t host_steps = 0;
+  int batch = 4;
+  gbees::Profiler prof;
+
+  uint32_t G() const { return grid_for(std::max<uint32_t>(nb_est, 64)); }
+
+  int sync_read() {
+    if (hipMemcpyAsync(&hsb, base + L.sb, sizeof(Scalars), hipMemcpyDeviceToHost, stream) != hipSuccess)
+      return fail(GBEES_E_DEVICE);
+    if (hipStreamSynchronize(stream) != hipSuccess) return fail(GBEES_E_DEVICE);
+    prof.harvest();
+    nb_est = std::max<uint32_t>(std::min<uint32_t>(hsb.nb, L.cap_b), 64);
+    host_steps = static_cast<int64_t>(hsb.steps);
+    if (hsb.status != 0) return fail(hsb.status == gbees::kErrRange ? GBEES_E_RANGE : GBEES_E_CAPACITY);
+    return GBEES_OK;
+  }
+  int fail(int code) {
+    if (status == GBEES_OK) status = code;
+    return code;
+  }
+};
+
+namespace {
+
+gbees_ctx* new_ctx(const gbees_config* cfg, void* arena, size_t bytes, void* stream, int* err) {
+  *err = GBEES_E_ARG;
+  if (!cfg || !arena) return nullptr;
+  Layout L;
+  if (!make_layout(*cfg, &L) || bytes < L.total) return nullptr;
+  auto* c = new (std::nothrow) gbees_ctx();
+  if (!c) return nullptr;
+  c->cfg = *cfg;
+  c->L = L;
+  c->base = static_cast<char*>(arena);
+  c->stream = static_cast<hipStream_t>(stream);
+  c->kt = gbees::kernel_table(effective_model(*cfg), cfg->n, cfg->precision);
+  if (cfg->precision == 1) {
+    fill_dev(c->d32, *cfg, L, c->base);
+    c->dev = &c->d32;
+  } else {
+    fill_dev(c->d64, *cfg, L, c->base);
+    c->dev = &c->d64;
+  }
+  std::memset(&c->hsb, 0, sizeof(c->hsb));
+  if (hipMemsetAsync(c->base, 0, L.zero_end, c->stream) != hipSuccess ||
+      hipMemsetAsync(c->base + L.zero_end, 0xFF, L.ff_end - L.zero_end, c->stream) != hipSuccess) {
+    delete c;
+    *err = GBEES_E_DEVICE;
+    return nullptr;
+  }
+  *err = GBEES_OK;
+  return c;
+}
+
+template <typename F>
+void with_dev(gbees_ctx* c, F f) {
+  if (c->cfg.precision == 1)
+    f(c->d32);
+  else
+    f(c->d64);
+}
+
+int check_ctx(gbees_ctx* c) {
+  if (!c) return GBEES_E_ARG;
+  if (c->status != GBEES_OK) return GBEES_E_STATE;
+  return GBEES_OK;
+}
+
+struct CellRow {
+  int32_t idx[6];
+  double p;
+};
+
+bool row_less(const CellRow& a, const CellRow& b, int n) {
+  for (int j = 0; j < n; ++j)
+    if (a.idx[j] != b.idx[j]) return a.idx[j] < b.idx[j];
+  return false;
+}
+
+// Bricks of the current grid copied to the host and expanded to cells.
+int host_cells(gbees_ctx* c, std::vector<CellRow>* rows) {
+  const int rc = c->sync_read();
+  if (rc != GBEES_OK) return rc;
+  const uint32_t nb = std::min<uint32_t>(c->hsb.nb, c->L.cap_b);
+  const int n = c->cfg.n;
+  std::vector<u64> key(nb), mask(nb);
+  std::vector<char> P(static_cast<size_t>(nb) * gbees::kLanes * c->L.real_size);
+  const size_t poff = c->hsb.cur ? c->L.P1 : c->L.P0;
+  if (nb > 0) {
+    if (hipMemcpyAsync(key.data(), c->base + c->L.key, nb * 8, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipMemcpyAsync(mask.data(), c->base + c->L.mask, nb * 8, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipMemcpyAsync(P.data(), c->base + poff, P.size(), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+      return c->fail(GBEES_E_DEVICE);
+  }
+  rows->clear();
+  for (uint32_t b = 0; b < nb; ++b) {
+    int64_t B[6] = {0, 0, 0, 0, 0, 0};
+    switch (n) {
+      case 1: gbees::unpack_key<1>(key[b], B); break;
+      case 2: gbees::unpack_key<2>(key[b], B); break;
+      case 3: gbees::unpack_key<3>(key[b], B); break;
+      case 4: gbees::unpack_key<4>(key[b], B); break;
+      case 5: gbees::unpack_key<5>(key[b], B); break;
+      default: gbees::unpack_key<6>(key[b], B); break;
+    }
+    for (int lane = 0; lane < gbees::kLanes; ++lane) {
+      if (!((mask[b] >> lane) & 1ull)) continue;
+      CellRow r;
+      std::memset(&r, 0, sizeof(r));
+      for (int j = 0; j < n; ++j) {
+        const int a = (lane >> gbees::brick_off(n, j)) & (gbees::brick_side(n, j) - 1);
+        r.idx[j] = static_cast<int32_t>(B[j] * gbees::brick_side(n, j) + a);
+      }
+      const size_t o = static_cast<size_t>(b) * gbees::kLanes + lane;
+      r.p = c->L.real_size == 4 ? static_cast<double>(reinterpret_cast<const float*>(P.data())[o])
+                                : reinterpret_cast<const double*>(P.data())[o];
+      rows->push_back(r);
+    }
+  }
+  std::sort(rows->begin(), rows->end(), [n](const CellRow& a, const CellRow& b) { return row_less(a, b, n); });
+  return GBEES_OK;
+}
+
+template <int N>
+u64 key_of_cell(const int32_t* idx, bool* ok) {
+  int64_t B[N];
+  for (int j = 0; j < N; ++j) {
+    const int64_t i = idx[j];
+    B[j] = (i >= 0) ? i / gbees::brick_side(N, j) : -((-i + gbees::brick_side(N, j) - 1) / gbees::brick_side(N, j));
+  }
+  *ok = gbees::brick_in_range<N>(B);
+  return *ok ? gbees::pack_key<N>(B) : 0ull;
+}
+
+u64 key_of_cell_n(int n, const int32_t* idx, bool* ok) {
+  switch (n) {
+    case 1: return key_of_cell<1>(idx, ok);
+    case 2: return key_of_cell<2>(idx, ok);
+    case 3: return key_of_cell<3>(idx, ok);
+    case 4: return key_of_cell<4>(idx, ok);
+    case 5: return key_of_cell<5>(idx, ok);
+    default: return key_of_cell<6>(idx, ok);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t gbees_arena_bytes(const gbees_config* cfg) {
+  Layout L;
+  if (!cfg || !make_layout(*cfg, &L)) return 0;
+  return L.total;
+}
+
+int gbees_init_gaussian(const gbees_config* cfg, void* arena, size_t arena_bytes, void* hip_stream, gbees_ctx** out) {
+  if (!out) return GBEES_E_ARG;
+  *out = nullptr;
+  if (!cfg || !(cfg->thresh_rel > 0.0 && cfg->thresh_rel < 1.0)) return GBEES_E_ARG;
+  double sinv[36];
+  if (!spd_inverse(cfg->n, cfg->cov, sinv)) return GBEES_E_ARG;
+  int err;
+  gbees_ctx* c = new_ctx(cfg, arena, arena_bytes, hip_stream, &err);
+  if (!c) return err;
+  const int n = cfg->n;
+  const double bound = 2.0 * std::log(1.0 / cfg->thresh_rel);
+  int64_t lo[6] = {}, cnt[6] = {};
+  double box = 1.0;
+  for (int j = 0; j < n; ++j) {
+    const int64_t r = static_cast<int64_t>(std::ceil(std::sqrt(bound * cfg->cov[j * n + j]) / cfg->h[j]));
+    const int64_t side = gbees::brick_side(n, j);
+    const int64_t blo = (-r >= 0) ? -r / side : -((r + side - 1) / side);
+    const int64_t bhi = r / side;
+    if (blo < -gbees::brick_limit(n) || bhi >= gbees::brick_limit(n)) {
+      delete c;
+      return GBEES_E_RANGE;
+    }
+    lo[j] = blo;
+    cnt[j] = bhi - blo + 1;
+    box *= static_cast<double>(cnt[j]);
+  }
+  if (box > 4.0e12) {
+    delete c;
+    return GBEES_E_ARG;
+  }
+  with_dev(c, [&](auto& d) {
+    std::memcpy(d.sinv, sinv, sizeof(sinv));
+    d.bound = bound;
+    d.box_count = 1;
+    for (int j = 0; j < n; ++j) {
+      d.box_lo[j] = lo[j];
+      d.box_n[j] = cnt[j];
+      d.box_count *= static_cast<uint64_t>(cnt[j]);
+    }
+  });
+  const uint64_t box_count = static_cast<uint64_t>(box);
+  uint64_t gb = (box_count + 63) / 64;
+  gb = std::min<uint64_t>(std::max<uint64_t>((gb + 7) / 8 * 8, 8), gbees::kMaxWG);
+  c->nb_est = static_cast<uint32_t>(std::min<uint64_t>(box_count, c->L.cap_b));
+  c->kt->init_gaussian(c->dev, c->stream, c->G(), static_cast<uint32_t>(gb));
+  const int rc = c->sync_read();
+  if (rc != GBEES_OK) {
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return GBEES_OK;
+}
+
+int gbees_init_cells(const gbees_config* cfg, const int32_t* idx, const double* P, int64_t count, double t0,
+                     void* arena, size_t arena_bytes, void* hip_stream, gbees_ctx** out) {
+  if (!out) return GBEES_E_ARG;
+  *out = nullptr;
+  if (!cfg || count < 0 || (count > 0 && (!idx || !P))) return GBEES_E_ARG;
+  int err;
+  gbees_ctx* c = new_ctx(cfg, arena, arena_bytes, hip_stream, &err);
+  if (!c) return err;
+  const int n = cfg->n;
+  // Group cells into bricks, bricks ordered by packed key.
+  std::unordered_map<u64, uint32_t> where;
+  std::vector<u64> keys;
+  for (int64_t k = 0; k < count; ++k) {
+    bool ok;
+    const u64 key = key_of_cell_n(n, idx + k * n, &ok);
+    if (!ok) {
+      delete c;
+      return GBEES_E_RANGE;
+    }
+    if (where.emplace(key, 0u).second) keys.push_back(key);
+  }
+  std::sort(keys.begin(), keys.end());
+  if (keys.size() > c->L.cap_b) {
+    delete c;
+    return GBEES_E_CAPACITY;
+  }
+  for (size_t b = 0; b < keys.size(); ++b) where[keys[b]] = static_cast<uint32_t>(b);
+  const size_t rs = c->L.real_size;
+  std::vector<u64> mask(keys.size(), 0ull);
+  std::vector<char> pbuf(keys.size() * gbees::kLanes * rs, 0);
+  for (int64_t k = 0; k < count; ++k) {
+    bool ok;
+    const u64 key = key_of_cell_n(n, idx + k * n, &ok);
+    const uint32_t b = where[key];
+    int lane = 0;
+    for (int j = 0; j < n; ++j) {
+      const int32_t i = idx[k * n + j];
+      const int side = gbees::brick_side(n, j);
+      const int a = ((i % side) + side) % side;
+      lane |= a << gbees::brick_off(n, j);
+    }
+    if ((mask[b] >> lane) & 1ull) {
+      delete c;
+      return GBEES_E_ARG;  // duplicate cell
+    }
+    mask[b] |= 1ull << lane;
+    const size_t o = static_cast<size_t>(b) * gbees::kLanes + lane;
+    if (rs == 4)
+      reinterpret_cast<float*>(pbuf.data())[o] = static_cast<float>(P[k]);
+    else
+      reinterpret_cast<double*>(pbuf.data())[o] = P[k];
+  }
+  Scalars s0;
+  std::memset(&s0, 0, sizeof(s0));
+  s0.nb = static_cast<uint32_t>(keys.size());
+  s0.t = t0;
+  s0.t_stop = t0;
+  bool okc = true;
+  if (!keys.empty()) {
+    okc = hipMemcpyAsync(c->base + c->L.key, keys.data(), keys.size() * 8, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+          hipMemcpyAsync(c->base + c->L.mask, mask.data(), mask.size() * 8, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+          hipMemcpyAsync(c->base + c->L.P0, pbuf.data(), pbuf.size(), hipMemcpyHostToDevice, c->stream) == hipSuccess;
+  }
+  okc = okc && hipMemcpyAsync(c->base + c->L.sb, &s0, sizeof(s0), hipMemcpyHostToDevice, c->stream) == hipSuccess;
+  if (!okc) {
+    delete c;
+    return GBEES_E_DEVICE;
+  }
+  c->nb_est = std::max<uint32_t>(s0.nb, 64);
+  c->kt->init_finish(c->dev, c->stream, c->G());
+  const int rc = c->sync_read();  // also keeps the host buffers alive until the copies finished
+  if (rc != GBEES_OK) {
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return GBEES_OK;
+}
+
+int gbees_step(gbees_ctx* c, double t_stop, int64_t max_steps, gbees_stats* out) {
+  int rc = check_ctx(c);
+  if (rc != GBEES_OK) return rc;
+  if (!std::isfinite(t_stop) || t_stop < c->hsb.t) return GBEES_E_ARG;
+  const bool prune_on = c->cfg.prune_every > 0;
+  const bool thr_on = c->cfg.thresh_rel > 0.0;
+  if (c->hsb.t < t_stop) {
+    c->kt->set_tstop(c->dev, c->stream, t_stop);
+    int64_t taken = 0;
+    while (true) {
+      int K = c->batch;
+      if (max_steps > 0) K = static_cast<int>(std::min<int64_t>(K, max_steps - taken));
+      const int64_t before = c->host_steps;
+      const uint32_t G = c->G();
+      for (int k = 0; k < K; ++k) {
+        c->kt->step(c->dev, c->stream, G, &c->prof);
+        ++c->host_steps;
+        if (prune_on && c->host_steps % c->cfg.prune_every == 0) {
+          if (thr_on)
+            c->kt->prune(c->dev, c->stream, G, true, &c->prof);
+          else
+            c->kt->normalise(c->dev, c->stream, G, gbees::kGateStep);
+        }
+      }
+      rc = c->sync_read();
+      if (rc != GBEES_OK) return rc;
+      taken += c->host_steps - before;
+      if (c->hsb.t >= t_stop) break;
+      if (max_steps > 0 && taken >= max_steps) break;
+      if (c->hsb.dt_last > 0.0) {
+        const double est = std::ceil((t_stop - c->hsb.t) / c->hsb.dt_last);
+        c->batch = static_cast<int>(std::min(std::max(est + 1.0, 1.0), 256.0));
+      } else {
+        c->batch = std::min(c->batch * 2, 256);
+      }
+    }
+  }
+  return gbees_get_stats(c, out);
+}
+
+int gbees_correct(gbees_ctx* c, int32_t component, double y, double sigma) {
+  const int rc = check_ctx(c);
+  if (rc != GBEES_OK) return rc;
+  if (component < 0 || component >= c->cfg.n || !(sigma > 0.0) || !std::isfinite(y)) return GBEES_E_ARG;
+  const bool prune = c->cfg.prune_every > 0 && c->cfg.thresh_rel > 0.0;
+  c->kt->correct(c->dev, c->stream, c->G(), component, y, sigma, prune);
+  return c->sync_read();
+}
+
+int gbees_marginals(gbees_ctx* c, uint32_t dim_mask, int64_t capacity, int32_t* idx_out, double* val_out,
+                    int64_t* count_out) {
+  int rc = check_ctx(c);
+  if (rc != GBEES_OK) return rc;
+  const int n = c->cfg.n;
+  if (dim_mask == 0 || (dim_mask >> n) != 0 || !count_out) return GBEES_E_ARG;
+  rc = c->sync_read();
+  if (rc != GBEES_OK) return rc;
+  int nm = 0;
+  for (int j = 0; j < n; ++j) nm += (dim_mask >> j) & 1u;
+  const u64 cells = std::max<u64>(c->hsb.cells, 1);
+  u64 tcap = 2;
+  while (tcap < 2 * cells) tcap <<= 1;
+  while (tcap > 2 && tcap * 32 > c->L.qbytes) tcap >>= 1;
+  c->kt->marginals(c->dev, c->stream, c->G(), dim_mask, tcap - 1);
+  rc = c->sync_read();
+  if (rc != GBEES_OK) return rc;
+  if (c->hsb.overflow) return GBEES_E_CAPACITY;
+  const uint32_t count = c->hsb.nb_new;
+  std::vector<u64> okey(count);
+  std::vector<double> oval(count);
+  const size_t off = c->L.Q + static_cast<size_t>(tcap) * 16;
+  if (count > 0 &&
+      (hipMemcpyAsync(okey.data(), c->base + off, count * 8, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+       hipMemcpyAsync(oval.data(), c->base + off + tcap * 8, count * 8, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+       hipStreamSynchronize(c->stream) != hipSuccess))
+    return c->fail(GBEES_E_DEVICE);
+  *count_out = count;
+  if (capacity < static_cast<int64_t>(count)) return GBEES_E_BUFFER;
+  if (count > 0 && (!idx_out || !val_out)) return GBEES_E_ARG;
+  double w = 1.0;
+  for (int j = 0; j < n; ++j)
+    if (!((dim_mask >> j) & 1u)) w = w * c->cfg.h[j];
+  const int kb = 63 / nm;
+  const int64_t bias = int64_t(1) << (kb - 1);
+  const u64 km = (kb >= 63) ? (~0ull >> 1) : ((1ull << kb) - 1);
+  std::vector<CellRow> rows(count);
+  for (uint32_t r = 0; r < count; ++r) {
+    std::memset(&rows[r], 0, sizeof(CellRow));
+    for (int q = 0; q < nm; ++q) rows[r].idx[q] = static_cast<int32_t>(static_cast<int64_t>((okey[r] >> (kb * q)) & km) - bias);
+    rows[r].p = oval[r] * w;
+  }
+  std::sort(rows.begin(), rows.end(), [nm](const CellRow& a, const CellRow& b) { return row_less(a, b, nm); });
+  for (uint32_t r = 0; r < count; ++r) {
+    for (int q = 0; q < nm; ++q) idx_out[static_cast<size_t>(r) * nm + q] = rows[r].idx[q];
+    val_out[r] = rows[r].p;
+  }
+  return GBEES_OK;
+}
+
+int gbees_export(gbees_ctx* c, int64_t capacity, int32_t* idx, double* P, int64_t* count, double* t) {
+  int rc = check_ctx(c);
+  if (rc != GBEES_OK) return rc;
+  if (!count) return GBEES_E_ARG;
+  std::vector<CellRow> rows;
+  rc = host_cells(c, &rows);
+  if (rc != GBEES_OK) return rc;
+  *count = static_cast<int64_t>(rows.size());
+  if (t) *t = c->hsb.t;
+  if (capacity < static_cast<int64_t>(rows.size())) return GBEES_E_BUFFER;
+  if (!rows.empty() && (!idx || !P)) return GBEES_E_ARG;
+  const int n = c->cfg.n;
+  for (size_t r = 0; r < rows.size(); ++r) {
+    for (int j = 0; j < n; ++j) idx[r * n + j] = rows[r].idx[j];
+    P[r] = rows[r].p;
+  }
+  return GBEES_OK;
+}
+
+int gbees_get_stats(gbees_ctx* c, gbees_stats* out) {
+  if (!c) return GBEES_E_ARG;
+  if (c->status == GBEES_OK) {
+    const int rc = c->sync_read();
+    if (rc != GBEES_OK) return rc;
+  } else {
+    hipMemcpyAsync(&c->hsb, c->base + c->L.sb, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream);
+    hipStreamSynchronize(c->stream);
+  }
+  if (out) {
+    double vol = 1.0;
+    for (int j = 0; j < c->cfg.n; ++j) vol = vol * c->cfg.h[j];
+    out->t = c->hsb.t;
+    out->dt_last = c->hsb.dt_last;
+    out->mass = vol * c->hsb.sum;
+    out->max_p = c->hsb.maxp;
+    double smax;
+    std::memcpy(&smax, &c->hsb.smax_bits, sizeof(smax));
+    out->smax = smax;
+    out->steps = static_cast<int64_t>(c->hsb.steps);
+    out->cell_updates = static_cast<int64_t>(c->hsb.cell_updates);
+    out->brick_updates = static_cast<int64_t>(c->hsb.brick_updates);
+    out->cells = static_cast<int64_t>(c->hsb.cells);
+    out->bricks = static_cast<int64_t>(std::min<uint32_t>(c->hsb.nb, c->L.cap_b));
+    out->prunes = static_cast<int64_t>(c->hsb.prunes);
+  }
+  return c->status;
+}
+
+int gbees_probe_stats(gbees_ctx* c, int64_t n_miss, double* mean_hit, double* mean_miss, double* load) {
+  int rc = check_ctx(c);
+  if (rc != GBEES_OK) return rc;
+  if (n_miss < 0) return GBEES_E_ARG;
+  rc = c->sync_read();
+  if (rc != GBEES_OK) return rc;
+  double* out2 = reinterpret_cast<double*>(c->base + c->L.dpart);
+  if (hipMemsetAsync(out2, 0, 2 * sizeof(double), c->stream) != hipSuccess) return c->fail(GBEES_E_DEVICE);
+  c->kt->probe(c->dev, c->stream, c->G(), static_cast<uint64_t>(n_miss), out2);
+  double h[2] = {0, 0};
+  if (hipMemcpyAsync(h, out2, sizeof(h), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return c->fail(GBEES_E_DEVICE);
+  const double nb = static_cast<double>(std::min<uint32_t>(c->hsb.nb, c->L.cap_b));
+  if (mean_hit) *mean_hit = nb > 0 ? h[0] / nb : 0.0;
+  if (mean_miss) *mean_miss = n_miss > 0 ? h[1] / static_cast<double>(n_miss) : 0.0;
+  if (load) *load = nb / static_cast<double>(c->L.hcap);
+  return GBEES_OK;
+}
+
+int gbees_profile(gbees_ctx* c, int enable) {
+  if (!c) return GBEES_E_ARG;
+  c->prof.on = enable != 0;
+  return GBEES_OK;
+}
+
+int gbees_profile_read(gbees_ctx* c, double* ms, int64_t* launches) {
+  if (!c) return GBEES_E_ARG;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return GBEES_E_DEVICE;
+  c->prof.harvest();
+  for (int k = 0; k < gbees::kProfKinds; ++k) {
+    if (ms) ms[k] = c->prof.ms[k];
+    if (launches) launches[k] = c->prof.launches[k];
+    c->prof.ms[k] = 0.0;
+    c->prof.launches[k] = 0;
+  }
+  return GBEES_OK;
+}
+
+int gbees_destroy(gbees_ctx* c) {
+  if (!c) return GBEES_E_ARG;
+  hipStreamSynchronize(c->stream);
+  c->prof.release();
+  delete c;
+  return GBEES_OK;
+}
+
+const char* gbees_strerror(int code) {
+  switch (code) {
+    case GBEES_OK: return "ok";
+    case GBEES_E_ARG: return "invalid argument";
+    case GBEES_E_CAPACITY: return "grid capacity exceeded";
+    case GBEES_E_RANGE: return "cell index out of the packable range";
+    case GBEES_E_DEVICE: return "HIP runtime error";
+    case GBEES_E_BUFFER: return "output buffer too small";
+    case GBEES_E_STATE: return "context is in an error state";
+    default: return "unknown error";
+  }
+}
+
+}  // extern "C"

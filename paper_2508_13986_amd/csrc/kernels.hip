@@ -1,0 +1,1324 @@
+// HIP kernels of the GBEES time step for gfx950 (arXiv 2508.13986).
+//
+// Per time step (Sec. 3, Fig. 1 flow: grow -> advect -> prune):
+//   k_grow       directional growth (Sec. 3.3) of cells that became above the
+//                threshold since the last prune; creates bricks via the hashtable;
+//                keeps max_i S_i of the grown grid (Eq. 8).
+//   k_grow_fix   links new bricks to their axis neighbours; finishes inserts whose
+//                brick was being published by another wave.
+//   k_dt         CFL time step, clamped to the stop time (Eq. 8).
+//   k_flux_a     per cell: transverse fluctuations T_j and corrected states Q_l.
+//   k_flux_b     per cell: DCU face fluxes of the corrected states (Eq. 7 with the
+//                corner-transport terms of Algorithm 1), optional MC-limited
+//                high-resolution term, conservative update, max/sum reductions.
+//   k_final_step commits t, dt, max P, sum P and flips the density buffers.
+// Every prune_every steps: mark (Algorithm 3), compact, rehash, relink, normalise.
+//
+// Gather form of Algorithm 1.  Summing the four scattered corrections of
+// Algorithm 1 that land on the backward l-face of cell i gives
+//   F_{i,l} = u+ Q_l(i - e_l) + u- Q_l(i),          u = f_{i - 1/2 e_l, l},
+//   Q_l(k)  = P_k - sum_{j != l} dt/(2 h_j) T_j(k),
+//   T_j(k)  = f+_{k-1/2e_j, j} (P_k - P_{k-e_j}) + [k+e_j in grid] f-_{k+1/2e_j, j} (P_{k+e_j} - P_k),
+// where a missing cell has P = 0, and only faces with both cells present count.
+// Both passes therefore touch axis neighbours only (distance <= 2 with the
+// high-resolution term).
+#include <hip/hip_runtime.h>
+
+#include "gbees_host.hpp"
+
+namespace gbees {
+
+// ---------------------------------------------------------------------------
+// Small helpers
+// ---------------------------------------------------------------------------
+template <typename Real>
+__device__ __forceinline__ Real rpos(Real v) { return v > Real(0) ? v : Real(0); }
+template <typename Real>
+__device__ __forceinline__ Real rneg(Real v) { return v < Real(0) ? v : Real(0); }
+
+// Value at distance `dist` along j: own brick via a lane shuffle, else the
+// neighbour brick's copy (0 if that brick does not exist).
+template <int N, typename T>
+__device__ __forceinline__ T gather(const T* base, size_t bmul, T own, uint32_t bm, uint32_t bp, int lane, int j, int dist) {
+  int which;
+  const int tl = nb_lane<N>(lane, j, dist, &which);
+  const T vin = __shfl(own, tl);
+  const uint32_t nbk = which < 0 ? bm : bp;
+  T vout = T(0);
+  if (which != 0 && nbk != kNone) vout = base[static_cast<size_t>(nbk) * bmul + tl];
+  return which == 0 ? vin : vout;
+}
+
+template <int N>
+__device__ __forceinline__ bool present(u64 mown, u64 mm, u64 mp, int lane, int j, int dist) {
+  int which;
+  const int tl = nb_lane<N>(lane, j, dist, &which);
+  const u64 m = which == 0 ? mown : (which < 0 ? mm : mp);
+  return (m >> tl) & 1ull;
+}
+
+// MC-limited high-resolution flux correction (LeVeque 2002, ch. 6) of one face:
+// 1/2 |u| (1 - dt |u| / h) phi(theta) W in division-free form.
+template <typename Real>
+__device__ __forceinline__ Real hr_term(Real u, Real dth, Real w, Real wup) {
+  if (w * wup <= Real(0)) return Real(0);
+  const Real au = u < Real(0) ? -u : u;
+  const Real aw = w < Real(0) ? -w : w, awu = wup < Real(0) ? -wup : wup;
+  const Real s = w + wup;
+  const Real as = s < Real(0) ? -s : s;
+  Real lim = fmin(as * Real(0.5), fmin(Real(2) * aw, Real(2) * awu));
+  lim = w > Real(0) ? lim : -lim;
+  return Real(0.5) * au * (Real(1) - dth * au) * lim;
+}
+
+// Workgroup reduction of (max, sum, count) into dpart[blockIdx] (fixed order).
+__device__ inline void wg_store3(double vmax, double vsum, double vcnt, double* dpart) {
+  __shared__ double sh[3][kWavesPerWG];
+  vmax = wave_max(vmax);
+  vsum = wave_sum(vsum);
+  vcnt = wave_sum(vcnt);
+  const int w = threadIdx.x >> 6;
+  if (lane_id() == 0) {
+    sh[0][w] = vmax;
+    sh[1][w] = vsum;
+    sh[2][w] = vcnt;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = sh[0][0], b = sh[1][0], c = sh[2][0];
+    for (int k = 1; k < kWavesPerWG; ++k) {
+      a = fmax(a, sh[0][k]);
+      b = b + sh[1][k];
+      c = c + sh[2][k];
+    }
+    dpart[blockIdx.x * kPartStride + 0] = a;
+    dpart[blockIdx.x * kPartStride + 1] = b;
+    dpart[blockIdx.x * kPartStride + 2] = c;
+  }
+}
+
+// Single-workgroup fixed-order reduction of G partials.
+__device__ inline void reduce_partials(const double* dpart, uint32_t G, double* omax, double* osum, double* ocnt) {
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (uint32_t i = threadIdx.x; i < G; i += blockDim.x) {
+    a = fmax(a, dpart[i * kPartStride + 0]);
+    b = b + dpart[i * kPartStride + 1];
+    c = c + dpart[i * kPartStride + 2];
+  }
+  __shared__ double sh[3][kWavesPerWG];
+  a = wave_max(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+  const int w = threadIdx.x >> 6;
+  if (lane_id() == 0) {
+    sh[0][w] = a;
+    sh[1][w] = b;
+    sh[2][w] = c;
+  }
+  __syncthreads();
+  a = sh[0][0];
+  b = sh[1][0];
+  c = sh[2][0];
+  for (int k = 1; k < kWavesPerWG; ++k) {
+    a = fmax(a, sh[0][k]);
+    b = b + sh[1][k];
+    c = c + sh[2][k];
+  }
+  *omax = a;
+  *osum = b;
+  *ocnt = c;
+}
+
+// ---------------------------------------------------------------------------
+// Scalar kernels (one wave)
+// ---------------------------------------------------------------------------
+enum ScalarOp : int {
+  kOpStepBegin = 0,
+  kOpDt,
+  kOpPruneBeginStep,
+  kOpPruneBeginAlways,
+  kOpPruneCommit,
+  kOpSetTStop,
+  kOpResetSmax,
+  kOpMargBegin
+};
+
+template <typename Real>
+__global__ void k_scalar(Dev<Real> d, int op, double arg) {
+  if (threadIdx.x != 0) return;
+  Scalars* sb = d.sb;
+  switch (op) {
+    case kOpStepBegin:
+      sb->run = (sb->status == 0 && sb->t < sb->t_stop) ? 1u : 0u;
+      sb->nb_old = sb->nb;
+      sb->ndeferred = 0;
+      break;
+    case kOpDt: {
+      if (!sb->run) break;
+      if (sb->status != 0 || sb->nb > d.cap_b || sb->ndeferred > d.ndef_cap) {
+        if (sb->status == 0) sb->status = kErrCapacity;
+        sb->run = 0;
+        break;
+      }
+      const double smax = bits_to_double(sb->smax_bits);
+      const double rem = sb->t_stop - sb->t;
+      double dt;
+      if (d.dt_fixed > 0.0)
+        dt = d.dt_fixed;
+      else
+        dt = (smax > 0.0) ? d.cfl / smax : rem;
+      const bool last = dt >= rem;
+      if (last) dt = rem;
+      sb->dt = dt;
+      sb->t_next = last ? sb->t_stop : sb->t + dt;
+      break;
+    }
+    case kOpPruneBeginStep:
+    case kOpPruneBeginAlways:
+      sb->prun = (sb->status == 0 && (op == kOpPruneBeginAlways || sb->run)) ? 1u : 0u;
+      if (sb->prun) {
+        sb->smax_bits = 0ull;
+        sb->nb_prev = sb->nb;
+      }
+      break;
+    case kOpPruneCommit:
+      if (!sb->prun) break;
+      sb->nb = sb->nb_new;
+      sb->cur ^= 1u;
+      sb->prunes += 1;
+      break;
+    case kOpSetTStop:
+      sb->t_stop = arg;
+      break;
+    case kOpResetSmax:
+      sb->smax_bits = 0ull;
+      break;
+    case kOpMargBegin:
+      sb->nb_new = 0;
+      sb->overflow = 0;
+      break;
+    default:
+      break;
+  }
+}
+
+// Commit the step: reductions of the updated densities, time, buffer flip.
+template <typename Real>
+__global__ void k_final_step(Dev<Real> d, uint32_t G) {
+  Scalars* sb = d.sb;
+  if (!sb->run) return;
+  double a, b, c;
+  reduce_partials(d.dpart, G, &a, &b, &c);
+  if (threadIdx.x == 0) {
+    sb->maxp = a;
+    sb->sum = b;
+    sb->cells = static_cast<u64>(c);
+    sb->cell_updates += static_cast<u64>(c);
+    sb->brick_updates += min(sb->nb, d.cap_b);
+    sb->steps += 1;
+    sb->dt_last = sb->dt;
+    sb->t = sb->t_next;
+    sb->cur ^= 1u;
+  }
+}
+
+// mode 0: sum -> normaliser z = V * sum; mode 1: max -> maxp; mode 2: max, sum, count (stats)
+template <typename Real>
+__global__ void k_final_reduce(Dev<Real> d, uint32_t G, int gate, int mode) {
+  if (!gate_open(d, gate)) return;
+  double a, b, c;
+  reduce_partials(d.dpart, G, &a, &b, &c);
+  if (threadIdx.x == 0) {
+    Scalars* sb = d.sb;
+    if (mode == 0) {
+      sb->sum = b;
+      sb->z = d.vol * b;
+      sb->cells = static_cast<u64>(c);
+    } else {
+      sb->maxp = a;
+      if (mode == 2) {
+        sb->sum = b;
+        sb->cells = static_cast<u64>(c);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fills, hashtable build, links
+// ---------------------------------------------------------------------------
+template <typename Real>
+__global__ void k_hash_clear(Dev<Real> d, int gate) {
+  if (!gate_open(d, gate)) return;
+  const uint64_t n = d.hmask + 1;
+  for (uint64_t i = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x) {
+    d.hkey[i] = kEmptyKey;
+    d.hval[i] = kNone;
+  }
+}
+
+template <typename Real>
+__global__ void k_hash_insert_all(Dev<Real> d, int gate) {
+  if (!gate_open(d, gate)) return;
+  const uint32_t nb = nb_of(d);
+  for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += gridDim.x * blockDim.x) {
+    bool won;
+    const uint64_t h = hash_claim(d, d.key[b], &won);
+    if (h == ~0ull) {
+      set_status(d.sb, kErrCapacity);
+      continue;
+    }
+    __hip_atomic_store(&d.hval[h], b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+template <int N>
+__device__ __forceinline__ uint64_t neighbour_key(uint64_t key, int j, int s, bool* ok) {
+  int64_t B[N];
+  unpack_key<N>(key, B);
+  B[j] += s;
+  *ok = brick_in_range<N>(B);
+  return *ok ? pack_key<N>(B) : 0ull;
+}
+
+// Link every brick in [lo, hi) to its 2n axis neighbours (thread per brick and direction);
+// with `both`, also point the neighbour back (used for bricks created this step).
+template <int N, typename Real>
+__device__ inline void link_range(const Dev<Real>& d, uint32_t lo, uint32_t hi, bool both) {
+  const uint64_t total = static_cast<uint64_t>(hi - lo) * (2 * N);
+  for (uint64_t t = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; t < total; t += uint64_t(gridDim.x) * blockDim.x) {
+    const uint32_t b = lo + static_cast<uint32_t>(t / (2 * N));
+    const int dd = static_cast<int>(t % (2 * N));
+    const int j = dd >> 1, s = (dd & 1) ? 1 : -1;
+    bool ok;
+    const uint64_t k = neighbour_key<N>(d.key[b], j, s, &ok);
+    uint32_t nbk = ok ? hash_find(d, k) : kNone;
+    if (nbk != kNone && nbk >= d.cap_b) nbk = kNone;
+    d.nbr[static_cast<size_t>(dd) * d.cap_b + b] = nbk;
+    if (both && nbk != kNone) d.nbr[static_cast<size_t>(dd ^ 1) * d.cap_b + nbk] = b;
+  }
+}
+
+template <int N, typename Real>
+__global__ void k_relink_all(Dev<Real> d, int gate) {
+  if (!gate_open(d, gate)) return;
+  link_range<N>(d, 0u, nb_of(d), false);
+}
+
+// ---------------------------------------------------------------------------
+// Reductions over the current densities, scaling, correction
+// ---------------------------------------------------------------------------
+template <int N, typename Real>
+__global__ __launch_bounds__(kWG) void k_reduce(Dev<Real> d, int gate) {
+  if (!gate_open(d, gate)) return;
+  const Real* P = cur_p(d);
+  const int lane = lane_id();
+  double vmax = 0.0, vsum = 0.0, vcnt = 0.0;
+  const WaveRange r = wave_range(nb_of(d));
+  for (uint32_t b = r.begin; b < r.end; b += r.step) {
+    const u64 m = d.mask[b];
+    if ((m >> lane) & 1ull) {
+      const double p = static_cast<double>(P[static_cast<size_t>(b) * kLanes + lane]);
+      vmax = fmax(vmax, p);
+      vsum += p;
+      vcnt += 1.0;
+    }
+  }
+  wg_store3(vmax, vsum, vcnt, d.dpart);
+}
+
+// P <- P / z (z = V * sum P, Sec. 4.5 normalisation); partial max of the result.
+template <int N, typename Real>
+__global__ __launch_bounds__(kWG) void k_scale(Dev<Real> d, int gate) {
+  if (!gate_open(d, gate)) return;
+  Real* P = cur_p_mut(d);
+  const double z = d.sb->z;
+  const bool do_scale = z > 0.0;
+  const int lane = lane_id();
+  double vmax = 0.0, vsum = 0.0, vcnt = 0.0;
+  const WaveRange r = wave_range(nb_of(d));
+  for (uint32_t b = r.begin; b < r.end; b += r.step) {
+    const size_t o = static_cast<size_t>(b) * kLanes + lane;
+    double p = static_cast<double>(P[o]);
+    if (do_scale) {
+      p = p / z;
+      P[o] = static_cast<Real>(p);
+      p = static_cast<double>(static_cast<Real>(p));
+    }
+    if ((d.mask[b] >> lane) & 1ull) {
+      vmax = fmax(vmax, p);
+      vsum += p;
+      vcnt += 1.0;
+    }
+  }
+  wg_store3(vmax, vsum, vcnt, d.dpart);
+}
+
+// Bayesian correction (Eq. 4): P_i *= exp(-(y - x_i,c)^2 / (2 sigma^2)); partial max.
+template <int N, typename Real>
+__global__ __launch_bounds__(kWG) void k_correct(Dev<Real> d, int comp, double y, double sigma) {
+  if (d.sb->status != 0) return;
+  Real* P = cur_p_mut(d);
+  const int lane = lane_id();
+  double vmax = 0.0, vsum = 0.0, vcnt = 0.0;
+  const WaveRange r = wave_range(nb_of(d));
+  for (uint32_t b = r.begin; b < r.end; b += r.step) {
+    int64_t B[N];
+    unpack_key<N>(d.key[b], B);
+    int32_t ii[N];
+    double xc[N];
+    cell_of<N>(d, B, lane, ii, xc);
+    const size_t o = static_cast<size_t>(b) * kLanes + lane;
+    double p = static_cast<double>(P[o]);
+    {
+#pragma clang fp contract(off)
+      const double dlt = y - xc[comp];
+      const double e = (dlt * dlt) / (2.0 * sigma * sigma);
+      p = p * exp(-e);
+    }
+    P[o] = static_cast<Real>(p);
+    if ((d.mask[b] >> lane) & 1ull) {
+      vmax = fmax(vmax, static_cast<double>(static_cast<Real>(p)));
+      vsum += p;
+      vcnt += 1.0;
+    }
+  }
+  wg_store3(vmax, vsum, vcnt, d.dpart);
+}
+
+// S over every cell of the grid (after initialisation).
+template <int N, int MODEL, typename Real>
+__global__ __launch_bounds__(kWG) void k_smax_all(Dev<Real> d) {
+  const int lane = lane_id();
+  double smax = 0.0;
+  const WaveRange r = wave_range(nb_of(d));
+  for (uint32_t b = r.begin; b < r.end; b += r.step) {
+    const u64 m = d.mask[b];
+    if ((m >> lane) & 1ull) {
+      int64_t B[N];
+      unpack_key<N>(d.key[b], B);
+      int32_t ii[N];
+      double xc[N];
+      cell_of<N>(d, B, lane, ii, xc);
+      smax = fmax(smax, cell_speed<MODEL, N>(d, xc, ii));
+    }
+  }
+  smax = wave_max(smax);
+  if (lane == 0 && smax > 0.0) atomicMax(&d.sb->smax_bits, double_to_bits(smax));
+}
+
+// ---------------------------------------------------------------------------
+// Initial condition (ellipsoid of the Gaussian)
+// ---------------------------------------------------------------------------
+template <int N, typename Real>
+__device__ __forceinline__ void box_brick(const Dev<Real>& d, uint64_t lin, int64_t* B) {
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    B[j] = d.box_lo[j] + static_cast<int64_t>(lin % static_cast<uint64_t>(d.box_n[j]));
+    lin /= static_cast<uint64_t>(d.box_n[j]);
+  }
+}
+
+// q(i) = y' S^-1 y with y = i h, in a fixed operation order.
+template <int N, typename Real>
+__device__ __forceinline__ double quad_form(const Dev<Real>& d, const int32_t* ii) {
+#pragma clang fp contract(off)
+  double y[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) y[j] = static_cast<double>(ii[j]) * d.h[j];
+  double q = 0.0;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    double row = 0.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) row = row + d.sinv[j * N + k] * y[k];
+    q = q + y[j] * row;
+  }
+  return q;
+}
+
+template <int N, typename Real>
+__global__ __launch_bounds__(kWG) void k_init_count(Dev<Real> d) {
+  uint64_t lo, hi;
+  wg_chunk(d.box_count, lo, hi);
+  const int lane = lane_id(), w = threadIdx.x >> 6;
+  uint32_t cnt = 0;
+  for (uint64_t i = lo + w; i < hi; i += kWavesPerWG) {
+    int64_t B[N];
+    box_brick<N>(d, i, B);
+    int32_t ii[N];
+    double xc[N];
+    cell_of<N>(d, B, lane, ii, xc);
+    if (ballot(quad_form<N>(d, ii) <= d.bound) != 0ull) ++cnt;
+  }
+  __shared__ uint32_t sh[kWavesPerWG];
+  if (lane == 0) sh[w] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t s = 0;
+    for (int k = 0; k < kWavesPerWG; ++k) s += sh[k];
+    d.part[blockIdx.x] = s;
+  }
+}
+
+template <int N, typename Real>
+__global__ __launch_bounds__(kWG) void k_init_write(Dev<Real> d) {
+  uint64_t lo, hi;
+  wg_chunk(d.box_count, lo, hi);
+  const int lane = lane_id(), w = threadIdx.x >> 6;
+  uint32_t base = d.part[blockIdx.x];
+  __shared__ uint32_t sh[kWavesPerWG];
+  for (uint64_t r0 = lo; r0 < hi; r0 += kWavesPerWG) {
+    const uint64_t i = r0 + w;
+    int64_t B[N];
+    int32_t ii[N];
+    double xc[N];
+    double q = 0.0;
+    u64 m = 0;
+    if (i < hi) {
+      box_brick<N>(d, i, B);
+      cell_of<N>(d, B, lane, ii, xc);
+      q = quad_form<N>(d, ii);
+      m = ballot(q <= d.bound);
+    }
+    if (lane == 0) sh[w] = (m != 0ull) ? 1u : 0u;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+    for (int k = 0; k < kWavesPerWG; ++k) {
+      before += (k < w) ? sh[k] : 0u;
+      total += sh[k];
+    }
+    if (m != 0ull) {
+      const uint32_t dst = base + before;
+      if (dst < d.cap_b) {
+        if (lane == 0) {
+          d.key[dst] = pack_key<N>(B);
+          d.mask[dst] = m;
+        }
+        const bool in = (m >> lane) & 1ull;
+        Real* P = d.P0;
+        P[static_cast<size_t>(dst) * kLanes + lane] = in ? static_cast<Real>(exp(-q / 2.0)) : Real(0);
+      }
+    }
+    base += total;
+    __syncthreads();
+  }
+}
+
+// Exclusive scan of part[0, G) in place; the total goes to part[G] and *total.
+__global__ void k_scan(uint32_t* part, uint32_t G, Scalars* sb, int gate, uint32_t* total, uint32_t cap) {
+  if (gate == kGatePrune && !sb->prun) return;
+  __shared__ uint32_t sh[kWG];
+  const uint32_t per = (G + kWG - 1) / kWG;
+  const uint32_t lo = threadIdx.x * per, hi = min(G, lo + per);
+  uint32_t s = 0;
+  for (uint32_t i = lo; i < hi; ++i) s += part[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (int k = 0; k < kWG; ++k) {
+      const uint32_t v = sh[k];
+      sh[k] = acc;
+      acc += v;
+    }
+    part[G] = acc;
+    if (acc > cap) {
+      atomicCAS(&sb->status, 0, static_cast<int32_t>(kErrCapacity));
+      acc = cap;
+    }
+    *total = acc;
+  }
+  __syncthreads();
+  uint32_t acc = sh[threadIdx.x];
+  for (uint32_t i = lo; i < hi; ++i) {
+    const uint32_t v = part[i];
+    part[i] = acc;
+    acc += v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Grow (Sec. 3.3, Algorithm 2 semantics as set union over the pre-grow grid)
+// ---------------------------------------------------------------------------
+// Adds the cells `bits` to the brick with coordinates TB (index tb, or kNone if
+// unknown).  Returns the largest S of the cells this call created (wave-uniform).
+template <int N, int MODEL, typename Real>
+__device__ double add_cells(const Dev<Real>& d, const int64_t* TB, uint32_t tb, u64 bits, int lane) {
+  if (tb == kNone) {
+    if (!brick_in_range<N>(TB)) {
+      if (lane == 0) set_status(d.sb, kErrRange);
+      return 0.0;
+    }
+    const uint64_t key = pack_key<N>(TB);
+    uint64_t hs = 0;
+    int won = 0;
+    if (lane == 0) {
+      bool w;
+      hs = hash_claim(d, key, &w);
+      won = w ? 1 : 0;
+    }
+    hs = __shfl(hs, 0);
+    won = __shfl(won, 0);
+    if (hs == ~0ull) {
+      if (lane == 0) set_status(d.sb, kErrCapacity);
+      return 0.0;
+    }
+    if (won) {
+      uint32_t slot = 0;
+      if (lane == 0) {
+        slot = atomicAdd(&d.sb->nb, 1u);
+        if (slot < d.cap_b) {
+          d.key[slot] = key;
+          __hip_atomic_store(&d.hval[hs], slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+          set_status(d.sb, kErrCapacity);
+        }
+      }
+      slot = __shfl(slot, 0);
+      if (slot >= d.cap_b) return 0.0;
+      tb = slot;
+    } else {
+      uint32_t v = 0;
+      if (lane == 0) v = __hip_atomic_load(&d.hval[hs], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      v = __shfl(v, 0);
+      if (v == kNone) {
+        // Claimed by another wave that has not published the brick index yet.
+        if (lane == 0) {
+          const uint32_t k = atomicAdd(&d.sb->ndeferred, 1u);
+          if (k < d.ndef_cap) {
+            d.defer[2 * static_cast<size_t>(k)] = hs;
+            d.defer[2 * static_cast<size_t>(k) + 1] = bits;
+          }
+        }
+        return 0.0;
+      }
+      tb = v;
+    }
+  }
+  u64 cur = 0;
+  if (lane == 0) cur = __hip_atomic_load(&d.mask[tb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  cur = __shfl(cur, 0);
+  if ((bits & ~cur) == 0ull) return 0.0;
+  u64 old = 0;
+  if (lane == 0) old = atomicOr(&d.mask[tb], bits);
+  old = __shfl(old, 0);
+  const u64 created = bits & ~old;
+  if (created == 0ull) return 0.0;
+  if (lane == 0) atomicAdd(&d.sb->inserted, static_cast<u64>(__popcll(created)));
+  double s = 0.0;
+  if ((created >> lane) & 1ull) {
+    int32_t ii[N];
+    double xc[N];
+    cell_of<N>(d, TB, lane, ii, xc);
+    s = cell_speed<MODEL, N>(d, xc, ii);
+  }
+  return wave_max(s);
+}
+
+template <typename Real>
+__device__ __forceinline__ uint32_t nbr_of(const Dev<Real>& d, uint32_t b, int j, int s) {
+  return b == kNone ? kNone : d.nbr[static_cast<size_t>(2 * j + (s > 0 ? 1 : 0)) * d.cap_b + b];
+}
+
+// Brick offset helpers for the grow/prune bit algebra: moving lanes by s along j.
+template <int N>
+__device__ __forceinline__ u64 in_lanes(int j, int s) {
+  return s > 0 ? ~lanes_at(N, j, brick_side(N, j) - 1) : ~lanes_at(N, j, 0);
+}
+template <int N>
+__device__ __forceinline__ u64 out_lanes(int j, int s) {
+  return s > 0 ? lanes_at(N, j, brick_side(N, j) - 1) : lanes_at(N, j, 0);
+}
+template <int N>
+__device__ __forceinline__ int sh_in(int j, int s) {
+  return s * brick_stride(N, j);
+}
+template <int N>
+__device__ __forceinline__ int sh_out(int j, int s) {
+  return -s * (brick_side(N, j) - 1) * brick_stride(N, j);
+}
+
+// Index of the brick at offset s e_j + r e_l from b through the link table (kNone if unknown).
+template <typename Real>
+__device__ __forceinline__ uint32_t diag_of(const Dev<Real>& d, uint32_t b, int j, int s, int l, int r) {
+  uint32_t t = nbr_of(d, nbr_of(d, b, j, s), l, r);
+  if (t == kNone) t = nbr_of(d, nbr_of(d, b, l, r), j, s);
+  return t;
+}
+
+template <int N, int MODEL, typename Real>
+__global__ __launch_bounds__(kWG) void k_grow(Dev<Real> d) {
+  Scalars* sb = d.sb;
+  if (!sb->run) return;
+  const uint32_t nb_old = sb->nb_old;
+  const Real* P = cur_p(d);
+  const bool thr0 = !(d.thresh_rel > 0.0);
+  const Real pstar = static_cast<Real>(d.thresh_rel * sb->maxp);
+  const int lane = lane_id();
+  double smax = 0.0;
+  const WaveRange rg = wave_range(nb_old);
+  for (uint32_t b = rg.begin; b < rg.end; b += rg.step) {
+    const u64 m = __hip_atomic_load(&d.mask[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const Real p0 = P[static_cast<size_t>(b) * kLanes + lane];
+    const bool src = ((m >> lane) & 1ull) && (thr0 ? (p0 != Real(0)) : (p0 >= pstar));
+    const u64 S = ballot(src);
+    const u64 dn = d.done[b];
+    const u64 todo = S & ~dn;
+    if (todo == 0ull) continue;
+    if (lane == 0) d.done[b] = dn | S;
+
+    int64_t B[N];
+    unpack_key<N>(d.key[b], B);
+    int32_t ii[N];
+    double xc[N];
+    cell_of<N>(d, B, lane, ii, xc);
+    const bool t = (todo >> lane) & 1ull;
+    u64 U[N], D[N];  // lanes with a downwind +e_j / -e_j neighbour
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      bool up = t, dw = t;
+      if (d.grow_mode == 0) {
+        up = t && face_vel_fwd<MODEL, N>(d, xc, ii, j) > 0.0;
+        dw = t && face_vel<MODEL, N>(d, xc, ii, j) < 0.0;
+      }
+      U[j] = ballot(up);
+      D[j] = ballot(dw);
+    }
+    u64 own = 0ull;
+    u64 ax[2 * N];
+#pragma unroll
+    for (int k = 0; k < 2 * N; ++k) ax[k] = 0ull;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+#pragma unroll
+      for (int si = 0; si < 2; ++si) {
+        const int s = si ? 1 : -1;
+        const u64 src_js = si ? U[j] : D[j];
+        own |= lsh(src_js & in_lanes<N>(j, s), sh_in<N>(j, s));
+        ax[2 * j + si] |= lsh(src_js & out_lanes<N>(j, s), sh_out<N>(j, s));
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+#pragma unroll
+      for (int l = j + 1; l < N; ++l) {
+#pragma unroll
+        for (int si = 0; si < 2; ++si) {
+#pragma unroll
+          for (int ri = 0; ri < 2; ++ri) {
+            const int s = si ? 1 : -1, r = ri ? 1 : -1;
+            const u64 both = (si ? U[j] : D[j]) & (ri ? U[l] : D[l]);
+            if (both == 0ull) continue;
+            own |= lsh(both & in_lanes<N>(j, s) & in_lanes<N>(l, r), sh_in<N>(j, s) + sh_in<N>(l, r));
+            ax[2 * j + si] |= lsh(both & out_lanes<N>(j, s) & in_lanes<N>(l, r), sh_out<N>(j, s) + sh_in<N>(l, r));
+            ax[2 * l + ri] |= lsh(both & in_lanes<N>(j, s) & out_lanes<N>(l, r), sh_in<N>(j, s) + sh_out<N>(l, r));
+            const u64 dg = lsh(both & out_lanes<N>(j, s) & out_lanes<N>(l, r), sh_out<N>(j, s) + sh_out<N>(l, r));
+            if (dg != 0ull) {
+              int64_t TB[N];
+#pragma unroll
+              for (int k = 0; k < N; ++k) TB[k] = B[k];
+              TB[j] += s;
+              TB[l] += r;
+              smax = fmax(smax, add_cells<N, MODEL>(d, TB, diag_of(d, b, j, s, l, r), dg, lane));
+            }
+          }
+        }
+      }
+    }
+    if (own != 0ull) smax = fmax(smax, add_cells<N, MODEL>(d, B, b, own, lane));
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+#pragma unroll
+      for (int si = 0; si < 2; ++si) {
+        if (ax[2 * j + si] == 0ull) continue;
+        int64_t TB[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) TB[k] = B[k];
+        TB[j] += si ? 1 : -1;
+        smax = fmax(smax, add_cells<N, MODEL>(d, TB, nbr_of(d, b, j, si ? 1 : -1), ax[2 * j + si], lane));
+      }
+    }
+  }
+  if (lane == 0 && smax > 0.0) atomicMax(&sb->smax_bits, double_to_bits(smax));
+}
+
+// Link the bricks created this step and finish inserts that found their brick unpublished.
+template <int N, int MODEL, typename Real>
+__global__ __launch_bounds__(kWG) void k_grow_fix(Dev<Real> d) {
+  Scalars* sb = d.sb;
+  if (!sb->run || sb->status != 0) return;
+  const uint32_t nb = min(sb->nb, d.cap_b), nb_old = sb->nb_old;
+  if (nb > nb_old) link_range<N>(d, nb_old, nb, true);
+  const uint32_t ndef = min(sb->ndeferred, d.ndef_cap);
+  const int lane = lane_id();
+  double smax = 0.0;
+  const uint32_t wid = blockIdx.x * kWavesPerWG + (threadIdx.x >> 6), nw = gridDim.x * kWavesPerWG;
+  for (uint32_t k = wid; k < ndef; k += nw) {
+    const uint64_t hs = d.defer[2 * static_cast<size_t>(k)];
+    const u64 bits = d.defer[2 * static_cast<size_t>(k) + 1];
+    const uint32_t tb = __hip_atomic_load(&d.hval[hs], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tb == kNone || tb >= d.cap_b) continue;
+    int64_t TB[N];
+    unpack_key<N>(d.key[tb], TB);
+    smax = fmax(smax, add_cells<N, MODEL>(d, TB, tb, bits, lane));
+  }
+  if (lane == 0 && smax > 0.0) atomicMax(&sb->smax_bits, double_to_bits(smax));
+}
+
+// ---------------------------------------------------------------------------
+// Flux pass A: transverse fluctuations and corrected states Q_l
+// ---------------------------------------------------------------------------
+template <int N, int MODEL, typename Real>
+__global__ __launch_bounds__(kWG) void k_flux_a(Dev<Real> d) {
+  const Scalars* sb = d.sb;
+  if (!sb->run) return;
+  const uint32_t nb = nb_of(d);
+  const Real* P = cur_p(d);
+  const double dt = sb->dt;
+  Real c[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) c[j] = static_cast<Real>(dt / (2.0 * d.h[j]));
+  const int lane = lane_id();
+  const WaveRange rg = wave_range(nb);
+  for (uint32_t b = rg.begin; b < rg.end; b += rg.step) {
+    const u64 m = d.mask[b];
+    int64_t B[N];
+    unpack_key<N>(d.key[b], B);
+    int32_t ii[N];
+    double xc[N];
+    cell_of<N>(d, B, lane, ii, xc);
+    const bool act = (m >> lane) & 1ull;
+    const Real p0 = P[static_cast<size_t>(b) * kLanes + lane];
+    Real T[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const uint32_t bm = nbr_of(d, b, j, -1), bp = nbr_of(d, b, j, 1);
+      const u64 mp = bp != kNone ? d.mask[bp] : 0ull;
+      const Real pm = gather<N>(P, kLanes, p0, bm, bp, lane, j, -1);
+      const Real pp = gather<N>(P, kLanes, p0, bm, bp, lane, j, 1);
+      const bool ep = present<N>(m, 0ull, mp, lane, j, 1);
+      const Real ub = static_cast<Real>(face_vel<MODEL, N>(d, xc, ii, j));
+      const Real uf = static_cast<Real>(face_vel_fwd<MODEL, N>(d, xc, ii, j));
+      T[j] = rpos(ub) * (p0 - pm) + (ep ? rneg(uf) * (pp - p0) : Real(0));
+    }
+    Real* Qb = d.Q + static_cast<size_t>(b) * N * kLanes + lane;
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      Real q = p0;
+#pragma unroll
+      for (int j = 0; j < N; ++j)
+        if (j != l) q = q - c[j] * T[j];
+      Qb[l * kLanes] = act ? q : Real(0);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Flux pass B: face fluxes, high-resolution term, conservative update
+// ---------------------------------------------------------------------------
+template <int N, int MODEL, typename Real>
+__global__ __launch_bounds__(kWG) void k_flux_b(Dev<Real> d) {
+  const Scalars* sb = d.sb;
+  if (!sb->run) return;
+  const uint32_t nb = nb_of(d);
+  const Real* P = cur_p(d);
+  Real* Pn = next_p(d);
+  const double dt = sb->dt;
+  Real dth[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) dth[j] = static_cast<Real>(dt / d.h[j]);
+  const bool hr = d.limiter != 0;
+  const int lane = lane_id();
+  double vmax = 0.0, vsum = 0.0, vcnt = 0.0;
+  const WaveRange rg = wave_range(nb);
+  for (uint32_t b = rg.begin; b < rg.end; b += rg.step) {
+    const u64 m = d.mask[b];
+    int64_t B[N];
+    unpack_key<N>(d.key[b], B);
+    int32_t ii[N];
+    double xc[N];
+    cell_of<N>(d, B, lane, ii, xc);
+    const bool act = (m >> lane) & 1ull;
+    const size_t o = static_cast<size_t>(b) * kLanes + lane;
+    const Real p0 = P[o];
+    const Real* Qb = d.Q + static_cast<size_t>(b) * N * kLanes;
+    Real acc = p0;
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      const uint32_t bm = nbr_of(d, b, l, -1), bp = nbr_of(d, b, l, 1);
+      const u64 mm = bm != kNone ? d.mask[bm] : 0ull, mp = bp != kNone ? d.mask[bp] : 0ull;
+      const bool em = present<N>(m, mm, mp, lane, l, -1), ep = present<N>(m, mm, mp, lane, l, 1);
+      const Real pm1 = gather<N>(P, kLanes, p0, bm, bp, lane, l, -1);
+      const Real pp1 = gather<N>(P, kLanes, p0, bm, bp, lane, l, 1);
+      const Real* Ql = d.Q + static_cast<size_t>(l) * kLanes;
+      const Real q = Qb[l * kLanes + lane];
+      const Real qm = gather<N>(Ql, static_cast<size_t>(N) * kLanes, q, bm, bp, lane, l, -1);
+      const Real qp = gather<N>(Ql, static_cast<size_t>(N) * kLanes, q, bm, bp, lane, l, 1);
+      const Real ub = static_cast<Real>(face_vel<MODEL, N>(d, xc, ii, l));
+      const Real uf = static_cast<Real>(face_vel_fwd<MODEL, N>(d, xc, ii, l));
+      Real fb = rpos(ub) * qm + rneg(ub) * q;
+      Real ff = rpos(uf) * q + rneg(uf) * qp;
+      if (hr) {
+        const Real pm2 = gather<N>(P, kLanes, p0, bm, bp, lane, l, -2);
+        const Real pp2 = gather<N>(P, kLanes, p0, bm, bp, lane, l, 2);
+        fb += hr_term(ub, dth[l], p0 - pm1, ub > Real(0) ? pm1 - pm2 : pp1 - p0);
+        ff += hr_term(uf, dth[l], pp1 - p0, uf > Real(0) ? p0 - pm1 : pp2 - pp1);
+      }
+      if (em) acc = acc + dth[l] * fb;
+      if (ep) acc = acc - dth[l] * ff;
+    }
+    const Real out = act ? acc : Real(0);
+    Pn[o] = out;
+    if (act) {
+      const double v = static_cast<double>(out);
+      vmax = fmax(vmax, v);
+      vsum += v;
+      vcnt += 1.0;
+    }
+  }
+  wg_store3(vmax, vsum, vcnt, d.dpart);
+}
+
+// ---------------------------------------------------------------------------
+// Prune (Sec. 3.3 upwind rule, Algorithm 3)
+// ---------------------------------------------------------------------------
+template <int N, typename Real>
+__global__ __launch_bounds__(kWG) void k_prune_above(Dev<Real> d) {
+  if (!d.sb->prun) return;
+  const Real* P = cur_p(d);
+  const Real pstar = static_cast<Real>(d.thresh_rel * d.sb->maxp);
+  const int lane = lane_id();
+  const WaveRange rg = wave_range(nb_of(d));
+  for (uint32_t b = rg.begin; b < rg.end; b += rg.step) {
+    const u64 m = d.mask[b];
+    const bool a = ((m >> lane) & 1ull) && (P[static_cast<size_t>(b) * kLanes + lane] >= pstar);
+    const u64 A = ballot(a);
+    if (lane == 0) d.abv[b] = A;
+  }
+}
+
+template <int N, int MODEL, typename Real>
+__global__ __launch_bounds__(kWG) void k_prune_mark(Dev<Real> d) {
+  Scalars* sb = d.sb;
+  if (!sb->prun) return;
+  const int lane = lane_id();
+  double smax = 0.0;
+  const WaveRange rg = wave_range(nb_of(d));
+  for (uint32_t b = rg.begin; b < rg.end; b += rg.step) {
+    const u64 m = d.mask[b];
+    const u64 A = d.abv[b];
+    const u64 below = m & ~A;  // present cells with P < p*
+    u64 keep = A;
+    int64_t B[N];
+    unpack_key<N>(d.key[b], B);
+    int32_t ii[N];
+    double xc[N];
+    cell_of<N>(d, B, lane, ii, xc);
+    if (below != 0ull) {
+      const bool bl = (below >> lane) & 1ull;
+      u64 U[N], D[N];  // below lanes with an upwind neighbour at +e_j / -e_j
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        U[j] = ballot(bl && face_vel_fwd<MODEL, N>(d, xc, ii, j) < 0.0);
+        D[j] = ballot(bl && face_vel<MODEL, N>(d, xc, ii, j) > 0.0);
+      }
+      u64 Aax[2 * N];
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        const uint32_t bm = nbr_of(d, b, j, -1), bp = nbr_of(d, b, j, 1);
+        Aax[2 * j] = bm != kNone ? d.abv[bm] : 0ull;
+        Aax[2 * j + 1] = bp != kNone ? d.abv[bp] : 0ull;
+      }
+      u64 k2 = 0ull;
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+#pragma unroll
+        for (int si = 0; si < 2; ++si) {
+          const int s = si ? 1 : -1;
+          const u64 src = si ? U[j] : D[j];
+          k2 |= src & in_lanes<N>(j, s) & lsh(A, -sh_in<N>(j, s));
+          k2 |= src & out_lanes<N>(j, s) & lsh(Aax[2 * j + si], -sh_out<N>(j, s));
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+#pragma unroll
+        for (int l = j + 1; l < N; ++l) {
+#pragma unroll
+          for (int si = 0; si < 2; ++si) {
+#pragma unroll
+            for (int ri = 0; ri < 2; ++ri) {
+              const int s = si ? 1 : -1, r = ri ? 1 : -1;
+              const u64 src = (si ? U[j] : D[j]) & (ri ? U[l] : D[l]);
+              if (src == 0ull) continue;
+              k2 |= src & in_lanes<N>(j, s) & in_lanes<N>(l, r) & lsh(A, -(sh_in<N>(j, s) + sh_in<N>(l, r)));
+              k2 |= src & out_lanes<N>(j, s) & in_lanes<N>(l, r) &
+                    lsh(Aax[2 * j + si], -(sh_out<N>(j, s) + sh_in<N>(l, r)));
+              k2 |= src & in_lanes<N>(j, s) & out_lanes<N>(l, r) &
+                    lsh(Aax[2 * l + ri], -(sh_in<N>(j, s) + sh_out<N>(l, r)));
+              const u64 g = src & out_lanes<N>(j, s) & out_lanes<N>(l, r);
+              if (g != 0ull) {
+                uint32_t t = diag_of(d, b, j, s, l, r);
+                if (t == kNone) {
+                  int64_t TB[N];
+#pragma unroll
+                  for (int k = 0; k < N; ++k) TB[k] = B[k];
+                  TB[j] += s;
+                  TB[l] += r;
+                  if (brick_in_range<N>(TB)) t = hash_find(d, pack_key<N>(TB));
+                }
+                const u64 At = (t != kNone && t < d.cap_b) ? d.abv[t] : 0ull;
+                k2 |= g & lsh(At, -(sh_out<N>(j, s) + sh_out<N>(l, r)));
+              }
+            }
+          }
+        }
+      }
+      keep |= k2 & below;
+    }
+    if (lane == 0) d.mask[b] = keep;
+    if ((keep >> lane) & 1ull) smax = fmax(smax, cell_speed<MODEL, N>(d, xc, ii));
+  }
+  smax = wave_max(smax);
+  if (lane == 0 && smax > 0.0) atomicMax(&sb->smax_bits, double_to_bits(smax));
+}
+
+// Stable compaction of the bricks that kept at least one cell.
+template <typename Real>
+__global__ __launch_bounds__(kWG) void k_compact_count(Dev<Real> d) {
+  if (!d.sb->prun) return;
+  uint64_t lo, hi;
+  wg_chunk(min(d.sb->nb_prev, d.cap_b), lo, hi);
+  uint32_t cnt = 0;
+  for (uint64_t b = lo + threadIdx.x; b < hi; b += blockDim.x) cnt += (d.mask[b] != 0ull) ? 1u : 0u;
+  __shared__ uint32_t sh[kWG];
+  sh[threadIdx.x] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t s = 0;
+    for (int k = 0; k < kWG; ++k) s += sh[k];
+    d.part[blockIdx.x] = s;
+  }
+}
+
+template <typename Real>
+__global__ __launch_bounds__(kWG) void k_compact_scatter(Dev<Real> d) {
+  if (!d.sb->prun) return;
+  uint64_t lo, hi;
+  wg_chunk(min(d.sb->nb_prev, d.cap_b), lo, hi);
+  const Real* P = cur_p(d);
+  Real* Pn = next_p(d);
+  u64* key2 = reinterpret_cast<u64*>(d.Q);
+  u64* mask2 = key2 + d.cap_b;
+  const int lane = lane_id(), w = threadIdx.x >> 6;
+  uint32_t base = d.part[blockIdx.x];
+  __shared__ uint32_t shw[kWavesPerWG];
+  __shared__ uint32_t src_b[kWG], dst_b[kWG];
+  __shared__ u64 msk[kWG];
+  for (uint64_t r0 = lo; r0 < hi; r0 += kWG) {
+    const uint64_t b = r0 + threadIdx.x;
+    const u64 m = b < hi ? d.mask[b] : 0ull;
+    const bool f = m != 0ull;
+    const u64 bal = ballot(f);
+    const uint32_t pre = static_cast<uint32_t>(__popcll(bal & ((1ull << lane) - 1ull)));
+    if (lane == 0) shw[w] = static_cast<uint32_t>(__popcll(bal));
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+    for (int k = 0; k < kWavesPerWG; ++k) {
+      before += (k < w) ? shw[k] : 0u;
+      total += shw[k];
+    }
+    const uint32_t dst = base + before + pre;
+    src_b[threadIdx.x] = f ? static_cast<uint32_t>(b) : kNone;
+    dst_b[threadIdx.x] = dst;
+    msk[threadIdx.x] = m;
+    if (f) {
+      key2[dst] = d.key[b];
+      mask2[dst] = m;
+    }
+    __syncthreads();
+    for (int e = w * kLanes; e < (w + 1) * kLanes; ++e) {
+      const uint32_t sbk = src_b[e];
+      if (sbk == kNone) continue;
+      const Real v = P[static_cast<size_t>(sbk) * kLanes + lane];
+      Pn[static_cast<size_t>(dst_b[e]) * kLanes + lane] = ((msk[e] >> lane) & 1ull) ? v : Real(0);
+    }
+    base += total;
+    __syncthreads();
+  }
+}
+
+template <typename Real>
+__global__ __launch_bounds__(kWG) void k_compact_finish(Dev<Real> d) {
+  if (!d.sb->prun) return;
+  const uint32_t nb_new = min(d.sb->nb_new, d.cap_b), nb_prev = min(d.sb->nb_prev, d.cap_b);
+  const u64* key2 = reinterpret_cast<const u64*>(d.Q);
+  const u64* mask2 = key2 + d.cap_b;
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  const uint64_t tid = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x;
+  for (uint64_t b = tid; b < nb_prev; b += stride) {
+    if (b < nb_new) {
+      d.key[b] = key2[b];
+      d.mask[b] = mask2[b];
+    } else {
+      d.mask[b] = 0ull;
+    }
+    d.done[b] = 0ull;
+  }
+  const uint64_t lo = uint64_t(nb_new) * kLanes, hi = uint64_t(nb_prev) * kLanes;
+  for (uint64_t i = lo + tid; i < hi; i += stride) {
+    d.P0[i] = Real(0);
+    d.P1[i] = Real(0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Marginals: scratch hashtable keyed by the projected cell index
+// ---------------------------------------------------------------------------
+template <int N, typename Real>
+__global__ __launch_bounds__(kWG) void k_marg_accumulate(Dev<Real> d, uint32_t dim_mask, uint64_t tmask) {
+  u64* tkey = reinterpret_cast<u64*>(d.Q);
+  double* tval = reinterpret_cast<double*>(tkey + tmask + 1);
+  const Real* P = cur_p(d);
+  const int lane = lane_id();
+  int nm = 0;
+  for (int j = 0; j < N; ++j) nm += (dim_mask >> j) & 1u;
+  const int kb = 63 / (nm > 0 ? nm : 1);
+  const int64_t bias = int64_t(1) << (kb - 1);
+  const WaveRange rg = wave_range(nb_of(d));
+  for (uint32_t b = rg.begin; b < rg.end; b += rg.step) {
+    const u64 m = d.mask[b];
+    if (!((m >> lane) & 1ull)) continue;
+    int64_t B[N];
+    unpack_key<N>(d.key[b], B);
+    int32_t ii[N];
+    double xc[N];
+    cell_of<N>(d, B, lane, ii, xc);
+    u64 key = 0;
+    int c = 0;
+    for (int j = 0; j < N; ++j)
+      if ((dim_mask >> j) & 1u) {
+        key |= static_cast<u64>(static_cast<int64_t>(ii[j]) + bias) << (kb * c);
+        ++c;
+      }
+    u64 h = mix64(key) & tmask;
+    for (uint64_t probe = 0; probe <= tmask; ++probe) {
+      u64 k = __hip_atomic_load(&tkey[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (k == kEmptyKey) {
+        u64 expect = kEmptyKey;
+        if (__hip_atomic_compare_exchange_strong(&tkey[h], &expect, key, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT))
+          k = key;
+        else
+          k = expect;
+      }
+      if (k == key) {
+        atomicAdd(&tval[h], static_cast<double>(P[static_cast<size_t>(b) * kLanes + lane]));
+        break;
+      }
+      h = (h + 1) & tmask;
+      if (probe == tmask) atomicOr(&d.sb->overflow, 1u);
+    }
+  }
+}
+
+template <typename Real>
+__global__ void k_fill_marg(Dev<Real> d, uint64_t tmask) {
+  u64* tkey = reinterpret_cast<u64*>(d.Q);
+  double* tval = reinterpret_cast<double*>(tkey + tmask + 1);
+  for (uint64_t i = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; i <= tmask; i += uint64_t(gridDim.x) * blockDim.x) {
+    tkey[i] = kEmptyKey;
+    tval[i] = 0.0;
+  }
+}
+
+// Compact the occupied table slots to the front: keys to tkey2[0, count), sums to tval2.
+template <typename Real>
+__global__ void k_marg_compact(Dev<Real> d, uint64_t tmask) {
+  u64* tkey = reinterpret_cast<u64*>(d.Q);
+  double* tval = reinterpret_cast<double*>(tkey + tmask + 1);
+  u64* okey = reinterpret_cast<u64*>(tval + tmask + 1);
+  double* oval = reinterpret_cast<double*>(okey + tmask + 1);
+  for (uint64_t i = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; i <= tmask; i += uint64_t(gridDim.x) * blockDim.x) {
+    if (tkey[i] == kEmptyKey) continue;
+    const uint32_t k = atomicAdd(&d.sb->nb_new, 1u);
+    okey[k] = tkey[i];
+    oval[k] = tval[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Probe statistics (Sec. 4.2): successful lookups of every brick key and
+// unsuccessful lookups of keys that are not in the table.
+// ---------------------------------------------------------------------------
+template <typename Real>
+__global__ void k_probe(Dev<Real> d, uint64_t n_miss, double* out) {
+  const uint32_t nb = nb_of(d);
+  double hit = 0.0, miss = 0.0;
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t i = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; i < nb + n_miss; i += stride) {
+    const u64 key = i < nb ? d.key[i] : (mix64(i * 0x9e3779b97f4a7c15ull + 12345ull) >> 1);
+    u64 h = mix64(key) & d.hmask;
+    double probes = 1.0;
+    for (uint64_t p = 0; p <= d.hmask; ++p) {
+      const u64 k = d.hkey[h];
+      if (k == key || k == kEmptyKey) break;
+      h = (h + 1) & d.hmask;
+      probes += 1.0;
+    }
+    if (i < nb)
+      hit += probes;
+    else
+      miss += probes;
+  }
+  hit = wave_sum(hit);
+  miss = wave_sum(miss);
+  if (lane_id() == 0) {
+    atomicAdd(&out[0], hit);
+    atomicAdd(&out[1], miss);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launch sequences
+// ---------------------------------------------------------------------------
+template <int N, int MODEL, typename Real>
+struct Ops {
+  static const Dev<Real>& D(const void* p) { return *static_cast<const Dev<Real>*>(p); }
+
+  static void rebuild_links(const Dev<Real>& d, hipStream_t s, uint32_t G, int gate) {
+    k_hash_clear<Real><<<G, kWG, 0, s>>>(d, gate);
+    k_hash_insert_all<Real><<<G, kWG, 0, s>>>(d, gate);
+    k_relink_all<N, Real><<<G, kWG, 0, s>>>(d, gate);
+  }
+
+  static void normalise_gated(const Dev<Real>& d, hipStream_t s, uint32_t G, int gate) {
+    k_reduce<N, Real><<<G, kWG, 0, s>>>(d, gate);
+    k_final_reduce<Real><<<1, kWG, 0, s>>>(d, G, gate, 0);
+    k_scale<N, Real><<<G, kWG, 0, s>>>(d, gate);
+    k_final_reduce<Real><<<1, kWG, 0, s>>>(d, G, gate, 2);
+  }
+
+  static void init_gaussian(const void* p, hipStream_t s, uint32_t G, uint32_t Gbox) {
+    const Dev<Real>& d = D(p);
+    k_init_count<N, Real><<<Gbox, kWG, 0, s>>>(d);
+    k_scan<<<1, kWG, 0, s>>>(d.part, Gbox, d.sb, kGateAlways, &d.sb->nb, d.cap_b);
+    k_init_write<N, Real><<<Gbox, kWG, 0, s>>>(d);
+    rebuild_links(d, s, G, kGateAlways);
+    k_scalar<Real><<<1, 64, 0, s>>>(d, kOpResetSmax, 0.0);
+    k_smax_all<N, MODEL, Real><<<G, kWG, 0, s>>>(d);
+    normalise_gated(d, s, G, kGateAlways);
+  }
+
+  static void init_finish(const void* p, hipStream_t s, uint32_t G) {
+    const Dev<Real>& d = D(p);
+    rebuild_links(d, s, G, kGateAlways);
+    k_scalar<Real><<<1, 64, 0, s>>>(d, kOpResetSmax, 0.0);
+    k_smax_all<N, MODEL, Real><<<G, kWG, 0, s>>>(d);
+    k_reduce<N, Real><<<G, kWG, 0, s>>>(d, kGateAlways);
+    k_final_reduce<Real><<<1, kWG, 0, s>>>(d, G, kGateAlways, 2);
+  }
+
+  static void step(const void* p, hipStream_t s, uint32_t G, Profiler* pf) {
+    const Dev<Real>& d = D(p);
+    k_scalar<Real><<<1, 64, 0, s>>>(d, kOpStepBegin, 0.0);
+    pf->begin(kProfGrow, s);
+    k_grow<N, MODEL, Real><<<G, kWG, 0, s>>>(d);
+    pf->end(s);
+    pf->begin(kProfGrowFix, s);
+    k_grow_fix<N, MODEL, Real><<<G, kWG, 0, s>>>(d);
+    pf->end(s);
+    k_scalar<Real><<<1, 64, 0, s>>>(d, kOpDt, 0.0);
+    pf->begin(kProfFluxA, s);
+    k_flux_a<N, MODEL, Real><<<G, kWG, 0, s>>>(d);
+    pf->end(s);
+    pf->begin(kProfFluxB, s);
+    k_flux_b<N, MODEL, Real><<<G, kWG, 0, s>>>(d);
+    pf->end(s);
+    k_final_step<Real><<<1, kWG, 0, s>>>(d, G);
+  }
+
+  static void prune(const void* p, hipStream_t s, uint32_t G, bool from_step, Profiler* pf) {
+    const Dev<Real>& d = D(p);
+    pf->begin(kProfPrune, s);
+    k_scalar<Real><<<1, 64, 0, s>>>(d, from_step ? kOpPruneBeginStep : kOpPruneBeginAlways, 0.0);
+    k_prune_above<N, Real><<<G, kWG, 0, s>>>(d);
+    k_prune_mark<N, MODEL, Real><<<G, kWG, 0, s>>>(d);
+    k_compact_count<Real><<<G, kWG, 0, s>>>(d);
+    k_scan<<<1, kWG, 0, s>>>(d.part, G, d.sb, kGatePrune, &d.sb->nb_new, d.cap_b);
+    k_compact_scatter<Real><<<G, kWG, 0, s>>>(d);
+    k_compact_finish<Real><<<G, kWG, 0, s>>>(d);
+    k_scalar<Real><<<1, 64, 0, s>>>(d, kOpPruneCommit, 0.0);
+    rebuild_links(d, s, G, kGatePrune);
+    normalise_gated(d, s, G, kGatePrune);
+    pf->end(s);
+  }
+
+  static void correct(const void* p, hipStream_t s, uint32_t G, int comp, double y, double sigma, bool do_prune) {
+    const Dev<Real>& d = D(p);
+    k_correct<N, Real><<<G, kWG, 0, s>>>(d, comp, y, sigma);
+    k_final_reduce<Real><<<1, kWG, 0, s>>>(d, G, kGateAlways, 2);
+    if (do_prune) {
+      Profiler none;
+      prune(p, s, G, false, &none);
+    } else {
+      normalise_gated(d, s, G, kGateAlways);
+    }
+  }
+
+  static void normalise(const void* p, hipStream_t s, uint32_t G, int gate) { normalise_gated(D(p), s, G, gate); }
+
+  static void set_tstop(const void* p, hipStream_t s, double t_stop) {
+    k_scalar<Real><<<1, 64, 0, s>>>(D(p), kOpSetTStop, t_stop);
+  }
+
+  static void marginals(const void* p, hipStream_t s, uint32_t G, uint32_t dim_mask, uint64_t tmask) {
+    const Dev<Real>& d = D(p);
+    k_scalar<Real><<<1, 64, 0, s>>>(d, kOpMargBegin, 0.0);
+    k_fill_marg<Real><<<G, kWG, 0, s>>>(d, tmask);
+    k_marg_accumulate<N, Real><<<G, kWG, 0, s>>>(d, dim_mask, tmask);
+    k_marg_compact<Real><<<G, kWG, 0, s>>>(d, tmask);
+  }
+
+  static void probe(const void* p, hipStream_t s, uint32_t G, uint64_t n_miss, double* out2) {
+    k_probe<Real><<<G, kWG, 0, s>>>(D(p), n_miss, out2);
+  }
+
+  static const KernelTable* table(int prec) {
+    static const KernelTable t = {N,          MODEL,   prec,      &init_gaussian, &init_finish, &step,
+                                  &prune,     &correct, &normalise, &set_tstop,     &marginals,   &probe};
+    return &t;
+  }
+};
+
+template <int N, int MODEL>
+static const KernelTable* pick(int precision) {
+  return precision == 0 ? Ops<N, MODEL, double>::table(0) : Ops<N, MODEL, float>::table(1);
+}
+
+const KernelTable* kernel_table(int model, int n, int precision) {
+  if (model == kModelL63) return n == 3 ? pick<3, kModelL63>(precision) : nullptr;
+  if (model == kModelL96) {
+    switch (n) {
+      case 4: return pick<4, kModelL96>(precision);
+      case 5: return pick<5, kModelL96>(precision);
+      case 6: return pick<6, kModelL96>(precision);
+      default: return nullptr;
+    }
+  }
+  if (model == kModelLinear) {
+    switch (n) {
+      case 1: return pick<1, kModelLinear>(precision);
+      case 2: return pick<2, kModelLinear>(precision);
+      case 3: return pick<3, kModelLinear>(precision);
+      case 4: return pick<4, kModelLinear>(precision);
+      case 5: return pick<5, kModelLinear>(precision);
+      case 6: return pick<6, kModelLinear>(precision);
+      default: return nullptr;
+    }
+  }
+  return nullptr;
+}
+
+}  // namespace gbees

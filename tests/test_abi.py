@@ -1,0 +1,74 @@
+"""The C-ABI library loads and exports every entry point include/gbees.h declares
+(CPU only: no compute calls), and its host-side validation behaves."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2508_13986_amd import gbees as G
+from paper_2508_13986_amd import scenarios as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "gbees.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gbees_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_entry_points():
+    names = _declared()
+    for must in ("gbees_init_gaussian", "gbees_step", "gbees_correct", "gbees_marginals", "gbees_export",
+                 "gbees_arena_bytes", "gbees_destroy"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = G.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def test_struct_layout_matches_header():
+    # gbees_config: 2 ints, 48+6+6+36 doubles, 3 doubles, 4 ints, int64, double
+    assert ctypes.sizeof(G.GbeesConfig) == 8 + 8 * 96 + 24 + 16 + 8 + 8
+    assert ctypes.sizeof(G.GbeesStats) == 5 * 8 + 6 * 8
+
+
+def test_arena_sizing_and_validation():
+    L = G.lib()
+    cfg = S.l63_small()
+    c = G.make_config(cfg, max_cells=1 << 16)
+    n1 = L.gbees_arena_bytes(ctypes.byref(c))
+    assert n1 > (1 << 16) * 16  # two density buffers at least
+    c2 = G.make_config(cfg, max_cells=1 << 18)
+    assert L.gbees_arena_bytes(ctypes.byref(c2)) > n1
+    bad = [dict(n=7), dict(model=9), dict(h=[0.0, 0.5, 0.5]), dict(thresh_rel=1.5), dict(cfl=0.0),
+           dict(limiter=3), dict(grow_mode=5), dict(precision=2), dict(prune_every=-1), dict(n=2)]
+    for b in bad:
+        cb = G.make_config(S.with_(cfg, **b), max_cells=1 << 16)
+        assert L.gbees_arena_bytes(ctypes.byref(cb)) == 0, b
+    small = G.make_config(cfg, max_cells=10)
+    assert L.gbees_arena_bytes(ctypes.byref(small)) == 0
+
+
+def test_strerror_names_every_code():
+    L = G.lib()
+    for code in (G.OK, G.E_ARG, G.E_CAPACITY, G.E_RANGE, G.E_DEVICE, G.E_BUFFER, G.E_STATE):
+        assert L.gbees_strerror(code).decode() not in ("", "unknown error")
+
+
+def test_init_rejects_bad_arguments_before_touching_the_device():
+    L = G.lib()
+    out = ctypes.c_void_p()
+    c = G.make_config(S.l63_small(), max_cells=1 << 16)
+    assert L.gbees_init_gaussian(ctypes.byref(c), None, 0, None, ctypes.byref(out)) == G.E_ARG
+    c.thresh_rel = 0.0  # the Gaussian initial grid needs 0 < thresh_rel < 1
+    assert L.gbees_init_gaussian(ctypes.byref(c), ctypes.c_void_p(1), 1 << 40, None, ctypes.byref(out)) == G.E_ARG
+    c = G.make_config(S.with_(S.l63_small(), cov=[[1, 2, 0], [2, 1, 0], [0, 0, 1]]), max_cells=1 << 16)
+    assert L.gbees_init_gaussian(ctypes.byref(c), ctypes.c_void_p(1), 1 << 40, None, ctypes.byref(out)) == G.E_ARG
+    assert L.gbees_step(None, 1.0, 0, None) == G.E_ARG
+    assert L.gbees_destroy(None) == G.E_ARG
