@@ -37,7 +37,7 @@ def flux_a_bytes_per_brick(n, real_size):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("gbees_dev.hpp", "kernels.hip"):
+    for f in ("gbees_dev.hpp", "kernels.hpp"):
         with open(os.path.join(ROOT, "paper_2508_13986_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -92,7 +92,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="l96_6d")
-    ap.add_argument("--max-cells", type=int, default=64 * 4_000_000)
+    ap.add_argument("--max-cells", type=int, default=64 * 8_000_000)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()

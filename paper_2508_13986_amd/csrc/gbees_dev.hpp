@@ -15,7 +15,19 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+
 namespace gbees {
+
+// Compile-time loop: f(std::integral_constant<int, I>{}) for I = 0 .. Count-1.
+template <typename F, int... I>
+__host__ __device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int Count, typename F>
+__host__ __device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, Count>{});
+}
 
 constexpr int kLanes = 64;
 constexpr int kWavesPerWG = 4;
@@ -49,6 +61,42 @@ __host__ __device__ constexpr uint64_t lanes_at(int n, int j, int v) {
     if (((L >> brick_off(n, j)) & (brick_side(n, j) - 1)) == v) m |= 1ull << L;
   return m;
 }
+// Moving one cell by s along j, seen as lane masks: `out` lanes leave the brick
+// (they land in the neighbour brick, shifted by sh_out lanes), `in` lanes stay
+// (shifted by sh_in lanes).
+template <int N, int J, int S>
+struct Dir {
+  static constexpr int side = brick_side(N, J), stride = brick_stride(N, J);
+  static constexpr uint64_t out = S > 0 ? lanes_at(N, J, side - 1) : lanes_at(N, J, 0);
+  static constexpr uint64_t in = ~out;
+  static constexpr int sh_in = S * stride;
+  static constexpr int sh_out = -S * (side - 1) * stride;
+};
+// Pair p of the ordered list (0,1), (0,2), ..., (n-2,n-1).
+__host__ __device__ constexpr int pair_j(int n, int p) {
+  int j = 0;
+  while (p >= n - 1 - j) {
+    p -= n - 1 - j;
+    ++j;
+  }
+  return j;
+}
+__host__ __device__ constexpr int pair_l(int n, int p) {
+  int j = 0;
+  while (p >= n - 1 - j) {
+    p -= n - 1 - j;
+    ++j;
+  }
+  return j + 1 + p;
+}
+template <int K>
+__host__ __device__ __forceinline__ unsigned long long lshc(unsigned long long m) {
+  if constexpr (K >= 0)
+    return m << K;
+  else
+    return m >> (-K);
+}
+
 // Bits per coordinate in a packed key; coordinates are biased by 2^(kb-1).
 __host__ __device__ constexpr int key_bits(int n) { return 63 / n; }
 // Brick coordinates allowed: the packed key must fit and cell indices stay int32.
@@ -178,7 +226,9 @@ __device__ inline WaveRange wave_range(uint32_t n) {
   const uint32_t xcd = blockIdx.x & 7u, slot = blockIdx.x >> 3, per = G >> 3;
   const uint32_t chunk = (n + 7u) / 8u;
   const uint32_t lo = min(n, xcd * chunk), hi = min(n, lo + chunk);
-  const uint32_t w = slot * kWavesPerWG + (threadIdx.x >> 6);
+  // readfirstlane tells the compiler the wave index is uniform, so brick-derived
+  // values (links, masks, keys, base pointers) live in scalar registers.
+  const uint32_t w = slot * kWavesPerWG + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   return WaveRange{lo + w, hi, per * kWavesPerWG};
 }
 

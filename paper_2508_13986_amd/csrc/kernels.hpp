@@ -1,4 +1,5 @@
 // HIP kernels of the GBEES time step for gfx950 (arXiv 2508.13986).
+// Included by the inst_*.hip translation units, which instantiate them per model.
 //
 // Per time step (Sec. 3, Fig. 1 flow: grow -> advect -> prune):
 //   k_grow       directional growth (Sec. 3.3) of cells that became above the
@@ -22,11 +23,16 @@
 // where a missing cell has P = 0, and only faces with both cells present count.
 // Both passes therefore touch axis neighbours only (distance <= 2 with the
 // high-resolution term).
+#pragma once
+
 #include <hip/hip_runtime.h>
 
 #include "gbees_host.hpp"
 
 namespace gbees {
+
+// Minimum resident waves per SIMD requested for the flux passes (caps VGPRs).
+constexpr int kFluxWavesPerEU = 4;
 
 // ---------------------------------------------------------------------------
 // Small helpers
@@ -36,25 +42,59 @@ __device__ __forceinline__ Real rpos(Real v) { return v > Real(0) ? v : Real(0);
 template <typename Real>
 __device__ __forceinline__ Real rneg(Real v) { return v < Real(0) ? v : Real(0); }
 
-// Value at distance `dist` along j: own brick via a lane shuffle, else the
-// neighbour brick's copy (0 if that brick does not exist).
+// Neighbour access inside a brick row.  For distance d along j (|d| <= side),
+// lane L's neighbour sits in lane rot(L, d) of either this brick or the brick
+// at sign(d) e_j: the lane whose local coordinate is (a_j + d) mod side.  Each
+// lane therefore offers either its own value or the neighbour brick's value at
+// its own position, and one rotate-shuffle delivers the neighbour to everyone.
+template <int N>
+__device__ __forceinline__ int rot_lane(int lane, int j, int d) {
+  const int side = brick_side(N, j), off = brick_off(N, j);
+  const int a = (lane >> off) & (side - 1);
+  const int a2 = (a + d + side) & (side - 1);
+  return lane + ((a2 - a) << off);
+}
+// Does lane L (coordinate a_j) serve its partner from its own brick?
+template <int N>
+__device__ __forceinline__ bool offers_own(int lane, int j, int d) {
+  const int side = brick_side(N, j);
+  const int a = (lane >> brick_off(N, j)) & (side - 1);
+  return d > 0 ? (a >= d) : (a < side + d);
+}
 template <int N, typename T>
-__device__ __forceinline__ T gather(const T* base, size_t bmul, T own, uint32_t bm, uint32_t bp, int lane, int j, int dist) {
-  int which;
-  const int tl = nb_lane<N>(lane, j, dist, &which);
-  const T vin = __shfl(own, tl);
-  const uint32_t nbk = which < 0 ? bm : bp;
-  T vout = T(0);
-  if (which != 0 && nbk != kNone) vout = base[static_cast<size_t>(nbk) * bmul + tl];
-  return which == 0 ? vin : vout;
+__device__ __forceinline__ T neighbour(T own, T other, int lane, int j, int d) {
+  const T offer = offers_own<N>(lane, j, d) ? own : other;
+  return (brick_side(N, j) == 2 && (d == 2 || d == -2)) ? other : __shfl(offer, rot_lane<N>(lane, j, d));
+}
+template <int N>
+__device__ __forceinline__ bool neighbour_present(u64 mown, u64 mother, int lane, int j, int d) {
+  const int side = brick_side(N, j);
+  const int a = (lane >> brick_off(N, j)) & (side - 1);
+  const bool own = (a + d >= 0) && (a + d < side);
+  return ((own ? mown : mother) >> rot_lane<N>(lane, j, d)) & 1ull;
 }
 
-template <int N>
-__device__ __forceinline__ bool present(u64 mown, u64 mm, u64 mp, int lane, int j, int dist) {
-  int which;
-  const int tl = nb_lane<N>(lane, j, dist, &which);
-  const u64 m = which == 0 ? mown : (which < 0 ? mm : mp);
-  return (m >> tl) & 1ull;
+// Compile-time-direction variants: J and Dd known, so the offer test is a bit
+// test and 2-wide dimensions use an XOR shuffle.
+template <int N, int J, int Dd, typename T>
+__device__ __forceinline__ T nbval(T own, T other, int lane) {
+  constexpr int side = brick_side(N, J), stride = brick_stride(N, J);
+  if constexpr (side == 2 && (Dd == 2 || Dd == -2)) {
+    return other;
+  } else {
+    const T offer = offers_own<N>(lane, J, Dd) ? own : other;
+    if constexpr (side == 2)
+      return __shfl_xor(offer, stride);
+    else
+      return __shfl(offer, rot_lane<N>(lane, J, Dd));
+  }
+}
+template <int N, int J, int Dd>
+__device__ __forceinline__ bool nbpresent(u64 mown, u64 mother, int lane) {
+  constexpr int side = brick_side(N, J), off = brick_off(N, J);
+  const int a = (lane >> off) & (side - 1);
+  const bool own = (a + Dd >= 0) && (a + Dd < side);
+  return ((own ? mown : mother) >> rot_lane<N>(lane, J, Dd)) & 1ull;
 }
 
 // MC-limited high-resolution flux correction (LeVeque 2002, ch. 6) of one face:
@@ -506,7 +546,7 @@ __global__ __launch_bounds__(kWG) void k_init_write(Dev<Real> d) {
 }
 
 // Exclusive scan of part[0, G) in place; the total goes to part[G] and *total.
-__global__ void k_scan(uint32_t* part, uint32_t G, Scalars* sb, int gate, uint32_t* total, uint32_t cap) {
+static __global__ void k_scan(uint32_t* part, uint32_t G, Scalars* sb, int gate, uint32_t* total, uint32_t cap) {
   if (gate == kGatePrune && !sb->prun) return;
   __shared__ uint32_t sh[kWG];
   const uint32_t per = (G + kWG - 1) / kWG;
@@ -544,7 +584,7 @@ __global__ void k_scan(uint32_t* part, uint32_t G, Scalars* sb, int gate, uint32
 // Adds the cells `bits` to the brick with coordinates TB (index tb, or kNone if
 // unknown).  Returns the largest S of the cells this call created (wave-uniform).
 template <int N, int MODEL, typename Real>
-__device__ double add_cells(const Dev<Real>& d, const int64_t* TB, uint32_t tb, u64 bits, int lane) {
+__device__ __forceinline__ double add_cells(const Dev<Real>& d, const int64_t* TB, uint32_t tb, u64 bits, int lane) {
   if (tb == kNone) {
     if (!brick_in_range<N>(TB)) {
       if (lane == 0) set_status(d.sb, kErrRange);
@@ -621,30 +661,63 @@ __device__ __forceinline__ uint32_t nbr_of(const Dev<Real>& d, uint32_t b, int j
   return b == kNone ? kNone : d.nbr[static_cast<size_t>(2 * j + (s > 0 ? 1 : 0)) * d.cap_b + b];
 }
 
-// Brick offset helpers for the grow/prune bit algebra: moving lanes by s along j.
-template <int N>
-__device__ __forceinline__ u64 in_lanes(int j, int s) {
-  return s > 0 ? ~lanes_at(N, j, brick_side(N, j) - 1) : ~lanes_at(N, j, 0);
-}
-template <int N>
-__device__ __forceinline__ u64 out_lanes(int j, int s) {
-  return s > 0 ? lanes_at(N, j, brick_side(N, j) - 1) : lanes_at(N, j, 0);
-}
-template <int N>
-__device__ __forceinline__ int sh_in(int j, int s) {
-  return s * brick_stride(N, j);
-}
-template <int N>
-__device__ __forceinline__ int sh_out(int j, int s) {
-  return -s * (brick_side(N, j) - 1) * brick_stride(N, j);
-}
-
 // Index of the brick at offset s e_j + r e_l from b through the link table (kNone if unknown).
 template <typename Real>
 __device__ __forceinline__ uint32_t diag_of(const Dev<Real>& d, uint32_t b, int j, int s, int l, int r) {
   uint32_t t = nbr_of(d, nbr_of(d, b, j, s), l, r);
   if (t == kNone) t = nbr_of(d, nbr_of(d, b, l, r), j, s);
   return t;
+}
+
+// Targets of one brick: 0 = the brick itself, 1 + 2j + si = the axis neighbour
+// at s e_j (si = s > 0), then for each pair j < l and signs (s, r) the edge
+// neighbour at s e_j + r e_l.  Count: 1 + 2n + 4 n(n-1)/2.
+__host__ __device__ constexpr int n_targets(int n) { return 1 + 2 * n + 2 * n * (n - 1); }
+
+template <int N>
+__device__ __forceinline__ int target_kind(int k, int* j, int* s, int* l, int* r) {
+  if (k == 0) return 0;
+  if (k < 1 + 2 * N) {
+    *j = (k - 1) >> 1;
+    *s = ((k - 1) & 1) ? 1 : -1;
+    return 1;
+  }
+  int q = k - 1 - 2 * N;
+  int p = q >> 2;
+  *s = ((q >> 1) & 1) ? 1 : -1;
+  *r = (q & 1) ? 1 : -1;
+  int jj = 0;
+  while (p >= N - 1 - jj) {
+    p -= N - 1 - jj;
+    ++jj;
+  }
+  *j = jj;
+  *l = jj + 1 + p;
+  return 2;
+}
+
+// Lane-parallel resolution of target k of brick b: its index (kNone if not
+// reachable through the links) and the chosen per-brick word (mask or abv).
+template <int N, typename Real>
+__device__ __forceinline__ uint32_t resolve_target(const Dev<Real>& d, uint32_t b, int k) {
+  if (k >= n_targets(N)) return kNone;
+  int j = 0, s = 0, l = 0, r = 0;
+  const int kind = target_kind<N>(k, &j, &s, &l, &r);
+  if (kind == 0) return b;
+  if (kind == 1) return nbr_of(d, b, j, s);
+  return diag_of(d, b, j, s, l, r);
+}
+
+__device__ __forceinline__ u64 readlane64(u64 v, int k) {
+  const uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(v), k);
+  const uint32_t hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(v >> 32), k);
+  return (static_cast<u64>(hi) << 32) | lo;
+}
+
+// Word w of target k, held by lane k (k < 64) or lane k - 64 of the second set.
+__device__ __forceinline__ u64 target_word(u64 w0, u64 w1, int k) { return k < 64 ? readlane64(w0, k) : readlane64(w1, k - 64); }
+__device__ __forceinline__ uint32_t target_index(uint32_t t0, uint32_t t1, int k) {
+  return k < 64 ? __builtin_amdgcn_readlane(t0, k) : __builtin_amdgcn_readlane(t1, k - 64);
 }
 
 template <int N, int MODEL, typename Real>
@@ -656,6 +729,9 @@ __global__ __launch_bounds__(kWG) void k_grow(Dev<Real> d) {
   const bool thr0 = !(d.thresh_rel > 0.0);
   const Real pstar = static_cast<Real>(d.thresh_rel * sb->maxp);
   const int lane = lane_id();
+  constexpr int NT = n_targets(N);
+  __shared__ u64 tbl_all[kWavesPerWG][128];
+  u64* tbl = tbl_all[threadIdx.x >> 6];
   double smax = 0.0;
   const WaveRange rg = wave_range(nb_old);
   for (uint32_t b = rg.begin; b < rg.end; b += rg.step) {
@@ -674,7 +750,7 @@ __global__ __launch_bounds__(kWG) void k_grow(Dev<Real> d) {
     double xc[N];
     cell_of<N>(d, B, lane, ii, xc);
     const bool t = (todo >> lane) & 1ull;
-    u64 U[N], D[N];  // lanes with a downwind +e_j / -e_j neighbour
+    u64 U[N], D[N];  // todo lanes with a downwind +e_j / -e_j neighbour
 #pragma unroll
     for (int j = 0; j < N; ++j) {
       bool up = t, dw = t;
@@ -685,58 +761,83 @@ __global__ __launch_bounds__(kWG) void k_grow(Dev<Real> d) {
       U[j] = ballot(up);
       D[j] = ballot(dw);
     }
+    // Candidate cells of every target brick (bit algebra on lane masks) into the
+    // wave's table: entry 0 the brick itself, 1 + 2j + si the axis neighbours,
+    // then the edge neighbours.
+    tbl[lane] = 0ull;
+    tbl[lane + 64] = 0ull;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     u64 own = 0ull;
     u64 ax[2 * N];
 #pragma unroll
     for (int k = 0; k < 2 * N; ++k) ax[k] = 0ull;
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-#pragma unroll
-      for (int si = 0; si < 2; ++si) {
-        const int s = si ? 1 : -1;
+    static_for<N>([&](auto Jc) {
+      constexpr int j = decltype(Jc)::value;
+      static_for<2>([&](auto Sc) {
+        constexpr int si = decltype(Sc)::value;
+        using Dj = Dir<N, j, si ? 1 : -1>;
         const u64 src_js = si ? U[j] : D[j];
-        own |= lsh(src_js & in_lanes<N>(j, s), sh_in<N>(j, s));
-        ax[2 * j + si] |= lsh(src_js & out_lanes<N>(j, s), sh_out<N>(j, s));
-      }
+        own |= lshc<Dj::sh_in>(src_js & Dj::in);
+        ax[2 * j + si] |= lshc<Dj::sh_out>(src_js & Dj::out);
+      });
+    });
+    static_for<N*(N - 1) / 2>([&](auto Pc) {
+      constexpr int pair = decltype(Pc)::value;
+      constexpr int j = pair_j(N, pair), l = pair_l(N, pair);
+      static_for<4>([&](auto Cc) {
+        constexpr int si = decltype(Cc)::value >> 1, ri = decltype(Cc)::value & 1;
+        using Dj = Dir<N, j, si ? 1 : -1>;
+        using Dl = Dir<N, l, ri ? 1 : -1>;
+        const u64 both = (si ? U[j] : D[j]) & (ri ? U[l] : D[l]);
+        if (both == 0ull) return;
+        own |= lshc<Dj::sh_in + Dl::sh_in>(both & Dj::in & Dl::in);
+        ax[2 * j + si] |= lshc<Dj::sh_out + Dl::sh_in>(both & Dj::out & Dl::in);
+        ax[2 * l + ri] |= lshc<Dj::sh_in + Dl::sh_out>(both & Dj::in & Dl::out);
+        const u64 dg = lshc<Dj::sh_out + Dl::sh_out>(both & Dj::out & Dl::out);
+        if (dg != 0ull && lane == 0) tbl[1 + 2 * N + 4 * pair + 2 * si + ri] = dg;
+      });
+    });
+    if (lane == 0) {
+      tbl[0] = own & ~m;
+#pragma unroll
+      for (int k = 0; k < 2 * N; ++k) tbl[1 + k] = ax[k];
     }
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-#pragma unroll
-      for (int l = j + 1; l < N; ++l) {
-#pragma unroll
-        for (int si = 0; si < 2; ++si) {
-#pragma unroll
-          for (int ri = 0; ri < 2; ++ri) {
-            const int s = si ? 1 : -1, r = ri ? 1 : -1;
-            const u64 both = (si ? U[j] : D[j]) & (ri ? U[l] : D[l]);
-            if (both == 0ull) continue;
-            own |= lsh(both & in_lanes<N>(j, s) & in_lanes<N>(l, r), sh_in<N>(j, s) + sh_in<N>(l, r));
-            ax[2 * j + si] |= lsh(both & out_lanes<N>(j, s) & in_lanes<N>(l, r), sh_out<N>(j, s) + sh_in<N>(l, r));
-            ax[2 * l + ri] |= lsh(both & in_lanes<N>(j, s) & out_lanes<N>(l, r), sh_in<N>(j, s) + sh_out<N>(l, r));
-            const u64 dg = lsh(both & out_lanes<N>(j, s) & out_lanes<N>(l, r), sh_out<N>(j, s) + sh_out<N>(l, r));
-            if (dg != 0ull) {
-              int64_t TB[N];
-#pragma unroll
-              for (int k = 0; k < N; ++k) TB[k] = B[k];
-              TB[j] += s;
-              TB[l] += r;
-              smax = fmax(smax, add_cells<N, MODEL>(d, TB, diag_of(d, b, j, s, l, r), dg, lane));
-            }
-          }
-        }
-      }
+    // Lane-parallel: resolve the targets that received candidates and keep the
+    // candidate cells not yet present.  (Wave-scope fence: lane 0 wrote the table.)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const u64 bits0 = tbl[lane];
+    const u64 bits1 = lane + 64 < NT ? tbl[lane + 64] : 0ull;
+    uint32_t t0 = kNone, t1 = kNone;
+    u64 need0 = 0ull, need1 = 0ull;
+    if (bits0 != 0ull) {
+      t0 = resolve_target<N>(d, b, lane);
+      need0 = bits0 & ~(t0 != kNone ? __hip_atomic_load(&d.mask[t0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull);
     }
-    if (own != 0ull) smax = fmax(smax, add_cells<N, MODEL>(d, B, b, own, lane));
+    if (bits1 != 0ull) {
+      t1 = resolve_target<N>(d, b, lane + 64);
+      need1 = bits1 & ~(t1 != kNone ? __hip_atomic_load(&d.mask[t1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull);
+    }
+    u64 todo_t[2] = {ballot(need0 != 0ull), ballot(need1 != 0ull)};
 #pragma unroll
-    for (int j = 0; j < N; ++j) {
-#pragma unroll
-      for (int si = 0; si < 2; ++si) {
-        if (ax[2 * j + si] == 0ull) continue;
+    for (int half = 0; half < 2; ++half) {
+      while (todo_t[half] != 0ull) {
+        const int kl = __builtin_ctzll(todo_t[half]);
+        todo_t[half] &= todo_t[half] - 1ull;
+        const int k = kl + 64 * half;
+        const u64 bits = readlane64(half ? bits1 : bits0, kl);
+        const uint32_t tk = __builtin_amdgcn_readlane(half ? t1 : t0, kl);
+        int j = 0, s = 0, l = 0, r = 0;
+        const int kind = target_kind<N>(k, &j, &s, &l, &r);
         int64_t TB[N];
 #pragma unroll
-        for (int k = 0; k < N; ++k) TB[k] = B[k];
-        TB[j] += si ? 1 : -1;
-        smax = fmax(smax, add_cells<N, MODEL>(d, TB, nbr_of(d, b, j, si ? 1 : -1), ax[2 * j + si], lane));
+        for (int q = 0; q < N; ++q) TB[q] = B[q];
+        if (kind >= 1) TB[j] += s;
+        if (kind == 2) TB[l] += r;
+        smax = fmax(smax, add_cells<N, MODEL>(d, TB, tk, bits, lane));
       }
     }
   }
@@ -753,7 +854,8 @@ __global__ __launch_bounds__(kWG) void k_grow_fix(Dev<Real> d) {
   const uint32_t ndef = min(sb->ndeferred, d.ndef_cap);
   const int lane = lane_id();
   double smax = 0.0;
-  const uint32_t wid = blockIdx.x * kWavesPerWG + (threadIdx.x >> 6), nw = gridDim.x * kWavesPerWG;
+  const uint32_t wid = blockIdx.x * kWavesPerWG + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t nw = gridDim.x * kWavesPerWG;
   for (uint32_t k = wid; k < ndef; k += nw) {
     const uint64_t hs = d.defer[2 * static_cast<size_t>(k)];
     const u64 bits = d.defer[2 * static_cast<size_t>(k) + 1];
@@ -770,7 +872,7 @@ __global__ __launch_bounds__(kWG) void k_grow_fix(Dev<Real> d) {
 // Flux pass A: transverse fluctuations and corrected states Q_l
 // ---------------------------------------------------------------------------
 template <int N, int MODEL, typename Real>
-__global__ __launch_bounds__(kWG) void k_flux_a(Dev<Real> d) {
+__global__ __launch_bounds__(kWG, kFluxWavesPerEU) void k_flux_a(Dev<Real> d) {
   const Scalars* sb = d.sb;
   if (!sb->run) return;
   const uint32_t nb = nb_of(d);
@@ -791,17 +893,21 @@ __global__ __launch_bounds__(kWG) void k_flux_a(Dev<Real> d) {
     const bool act = (m >> lane) & 1ull;
     const Real p0 = P[static_cast<size_t>(b) * kLanes + lane];
     Real T[N];
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
+    static_for<N>([&](auto Jc) {
+      constexpr int j = decltype(Jc)::value;
       const uint32_t bm = nbr_of(d, b, j, -1), bp = nbr_of(d, b, j, 1);
+      const Real* Pmb = P + static_cast<size_t>(bm) * kLanes;
+      const Real* Ppb = P + static_cast<size_t>(bp) * kLanes;
+      const Real Pm = bm != kNone ? Pmb[lane] : Real(0);
+      const Real Pp = bp != kNone ? Ppb[lane] : Real(0);
       const u64 mp = bp != kNone ? d.mask[bp] : 0ull;
-      const Real pm = gather<N>(P, kLanes, p0, bm, bp, lane, j, -1);
-      const Real pp = gather<N>(P, kLanes, p0, bm, bp, lane, j, 1);
-      const bool ep = present<N>(m, 0ull, mp, lane, j, 1);
+      const Real pm = nbval<N, j, -1>(p0, Pm, lane);
+      const Real pp = nbval<N, j, 1>(p0, Pp, lane);
+      const bool ep = nbpresent<N, j, 1>(m, mp, lane);
       const Real ub = static_cast<Real>(face_vel<MODEL, N>(d, xc, ii, j));
       const Real uf = static_cast<Real>(face_vel_fwd<MODEL, N>(d, xc, ii, j));
       T[j] = rpos(ub) * (p0 - pm) + (ep ? rneg(uf) * (pp - p0) : Real(0));
-    }
+    });
     Real* Qb = d.Q + static_cast<size_t>(b) * N * kLanes + lane;
 #pragma unroll
     for (int l = 0; l < N; ++l) {
@@ -818,7 +924,7 @@ __global__ __launch_bounds__(kWG) void k_flux_a(Dev<Real> d) {
 // Flux pass B: face fluxes, high-resolution term, conservative update
 // ---------------------------------------------------------------------------
 template <int N, int MODEL, typename Real>
-__global__ __launch_bounds__(kWG) void k_flux_b(Dev<Real> d) {
+__global__ __launch_bounds__(kWG, kFluxWavesPerEU) void k_flux_b(Dev<Real> d) {
   const Scalars* sb = d.sb;
   if (!sb->run) return;
   const uint32_t nb = nb_of(d);
@@ -844,30 +950,37 @@ __global__ __launch_bounds__(kWG) void k_flux_b(Dev<Real> d) {
     const Real p0 = P[o];
     const Real* Qb = d.Q + static_cast<size_t>(b) * N * kLanes;
     Real acc = p0;
-#pragma unroll
-    for (int l = 0; l < N; ++l) {
+    static_for<N>([&](auto Lc) {
+      constexpr int l = decltype(Lc)::value;
       const uint32_t bm = nbr_of(d, b, l, -1), bp = nbr_of(d, b, l, 1);
+      const Real* Pmb = P + static_cast<size_t>(bm) * kLanes;
+      const Real* Ppb = P + static_cast<size_t>(bp) * kLanes;
+      const Real* Qmb = d.Q + (static_cast<size_t>(bm) * N + l) * kLanes;
+      const Real* Qpb = d.Q + (static_cast<size_t>(bp) * N + l) * kLanes;
+      const Real Pm = bm != kNone ? Pmb[lane] : Real(0);
+      const Real Pp = bp != kNone ? Ppb[lane] : Real(0);
+      const Real Qm = bm != kNone ? Qmb[lane] : Real(0);
+      const Real Qp = bp != kNone ? Qpb[lane] : Real(0);
       const u64 mm = bm != kNone ? d.mask[bm] : 0ull, mp = bp != kNone ? d.mask[bp] : 0ull;
-      const bool em = present<N>(m, mm, mp, lane, l, -1), ep = present<N>(m, mm, mp, lane, l, 1);
-      const Real pm1 = gather<N>(P, kLanes, p0, bm, bp, lane, l, -1);
-      const Real pp1 = gather<N>(P, kLanes, p0, bm, bp, lane, l, 1);
-      const Real* Ql = d.Q + static_cast<size_t>(l) * kLanes;
       const Real q = Qb[l * kLanes + lane];
-      const Real qm = gather<N>(Ql, static_cast<size_t>(N) * kLanes, q, bm, bp, lane, l, -1);
-      const Real qp = gather<N>(Ql, static_cast<size_t>(N) * kLanes, q, bm, bp, lane, l, 1);
+      const bool em = nbpresent<N, l, -1>(m, mm, lane), ep = nbpresent<N, l, 1>(m, mp, lane);
+      const Real pm1 = nbval<N, l, -1>(p0, Pm, lane);
+      const Real pp1 = nbval<N, l, 1>(p0, Pp, lane);
+      const Real qm = nbval<N, l, -1>(q, Qm, lane);
+      const Real qp = nbval<N, l, 1>(q, Qp, lane);
       const Real ub = static_cast<Real>(face_vel<MODEL, N>(d, xc, ii, l));
       const Real uf = static_cast<Real>(face_vel_fwd<MODEL, N>(d, xc, ii, l));
       Real fb = rpos(ub) * qm + rneg(ub) * q;
       Real ff = rpos(uf) * q + rneg(uf) * qp;
       if (hr) {
-        const Real pm2 = gather<N>(P, kLanes, p0, bm, bp, lane, l, -2);
-        const Real pp2 = gather<N>(P, kLanes, p0, bm, bp, lane, l, 2);
+        const Real pm2 = nbval<N, l, -2>(p0, Pm, lane);
+        const Real pp2 = nbval<N, l, 2>(p0, Pp, lane);
         fb += hr_term(ub, dth[l], p0 - pm1, ub > Real(0) ? pm1 - pm2 : pp1 - p0);
         ff += hr_term(uf, dth[l], pp1 - p0, uf > Real(0) ? p0 - pm1 : pp2 - pp1);
       }
       if (em) acc = acc + dth[l] * fb;
       if (ep) acc = acc - dth[l] * ff;
-    }
+    });
     const Real out = act ? acc : Real(0);
     Pn[o] = out;
     if (act) {
@@ -916,6 +1029,32 @@ __global__ __launch_bounds__(kWG) void k_prune_mark(Dev<Real> d) {
     double xc[N];
     cell_of<N>(d, B, lane, ii, xc);
     if (below != 0ull) {
+      // Above-threshold lanes of every target brick, one target per lane.
+      uint32_t t0 = resolve_target<N>(d, b, lane), t1 = resolve_target<N>(d, b, lane + 64);
+      if (t0 == kNone && lane < n_targets(N)) {
+        int j = 0, s = 0, l = 0, r = 0;
+        if (target_kind<N>(lane, &j, &s, &l, &r) == 2) {
+          int64_t TB[N];
+#pragma unroll
+          for (int q = 0; q < N; ++q) TB[q] = B[q];
+          TB[j] += s;
+          TB[l] += r;
+          if (brick_in_range<N>(TB)) t0 = hash_find(d, pack_key<N>(TB));
+        }
+      }
+      if (t1 == kNone && lane + 64 < n_targets(N)) {
+        int j = 0, s = 0, l = 0, r = 0;
+        if (target_kind<N>(lane + 64, &j, &s, &l, &r) == 2) {
+          int64_t TB[N];
+#pragma unroll
+          for (int q = 0; q < N; ++q) TB[q] = B[q];
+          TB[j] += s;
+          TB[l] += r;
+          if (brick_in_range<N>(TB)) t1 = hash_find(d, pack_key<N>(TB));
+        }
+      }
+      const u64 a0 = (t0 != kNone && t0 < d.cap_b) ? d.abv[t0] : 0ull;
+      const u64 a1 = (t1 != kNone && t1 < d.cap_b) ? d.abv[t1] : 0ull;
       const bool bl = (below >> lane) & 1ull;
       u64 U[N], D[N];  // below lanes with an upwind neighbour at +e_j / -e_j
 #pragma unroll
@@ -923,58 +1062,34 @@ __global__ __launch_bounds__(kWG) void k_prune_mark(Dev<Real> d) {
         U[j] = ballot(bl && face_vel_fwd<MODEL, N>(d, xc, ii, j) < 0.0);
         D[j] = ballot(bl && face_vel<MODEL, N>(d, xc, ii, j) > 0.0);
       }
-      u64 Aax[2 * N];
-#pragma unroll
-      for (int j = 0; j < N; ++j) {
-        const uint32_t bm = nbr_of(d, b, j, -1), bp = nbr_of(d, b, j, 1);
-        Aax[2 * j] = bm != kNone ? d.abv[bm] : 0ull;
-        Aax[2 * j + 1] = bp != kNone ? d.abv[bp] : 0ull;
-      }
       u64 k2 = 0ull;
-#pragma unroll
-      for (int j = 0; j < N; ++j) {
-#pragma unroll
-        for (int si = 0; si < 2; ++si) {
-          const int s = si ? 1 : -1;
+      static_for<N>([&](auto Jc) {
+        constexpr int j = decltype(Jc)::value;
+        static_for<2>([&](auto Sc) {
+          constexpr int si = decltype(Sc)::value;
+          using Dj = Dir<N, j, si ? 1 : -1>;
           const u64 src = si ? U[j] : D[j];
-          k2 |= src & in_lanes<N>(j, s) & lsh(A, -sh_in<N>(j, s));
-          k2 |= src & out_lanes<N>(j, s) & lsh(Aax[2 * j + si], -sh_out<N>(j, s));
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < N; ++j) {
-#pragma unroll
-        for (int l = j + 1; l < N; ++l) {
-#pragma unroll
-          for (int si = 0; si < 2; ++si) {
-#pragma unroll
-            for (int ri = 0; ri < 2; ++ri) {
-              const int s = si ? 1 : -1, r = ri ? 1 : -1;
-              const u64 src = (si ? U[j] : D[j]) & (ri ? U[l] : D[l]);
-              if (src == 0ull) continue;
-              k2 |= src & in_lanes<N>(j, s) & in_lanes<N>(l, r) & lsh(A, -(sh_in<N>(j, s) + sh_in<N>(l, r)));
-              k2 |= src & out_lanes<N>(j, s) & in_lanes<N>(l, r) &
-                    lsh(Aax[2 * j + si], -(sh_out<N>(j, s) + sh_in<N>(l, r)));
-              k2 |= src & in_lanes<N>(j, s) & out_lanes<N>(l, r) &
-                    lsh(Aax[2 * l + ri], -(sh_in<N>(j, s) + sh_out<N>(l, r)));
-              const u64 g = src & out_lanes<N>(j, s) & out_lanes<N>(l, r);
-              if (g != 0ull) {
-                uint32_t t = diag_of(d, b, j, s, l, r);
-                if (t == kNone) {
-                  int64_t TB[N];
-#pragma unroll
-                  for (int k = 0; k < N; ++k) TB[k] = B[k];
-                  TB[j] += s;
-                  TB[l] += r;
-                  if (brick_in_range<N>(TB)) t = hash_find(d, pack_key<N>(TB));
-                }
-                const u64 At = (t != kNone && t < d.cap_b) ? d.abv[t] : 0ull;
-                k2 |= g & lsh(At, -(sh_out<N>(j, s) + sh_out<N>(l, r)));
-              }
-            }
-          }
-        }
-      }
+          if (src == 0ull) return;
+          k2 |= src & Dj::in & lshc<-Dj::sh_in>(A);
+          k2 |= src & Dj::out & lshc<-Dj::sh_out>(target_word(a0, a1, 1 + 2 * j + si));
+        });
+      });
+      static_for<N*(N - 1) / 2>([&](auto Pc) {
+        constexpr int pair = decltype(Pc)::value;
+        constexpr int j = pair_j(N, pair), l = pair_l(N, pair);
+        static_for<4>([&](auto Cc) {
+          constexpr int si = decltype(Cc)::value >> 1, ri = decltype(Cc)::value & 1;
+          using Dj = Dir<N, j, si ? 1 : -1>;
+          using Dl = Dir<N, l, ri ? 1 : -1>;
+          const u64 src = (si ? U[j] : D[j]) & (ri ? U[l] : D[l]);
+          if (src == 0ull) return;
+          k2 |= src & Dj::in & Dl::in & lshc<-(Dj::sh_in + Dl::sh_in)>(A);
+          k2 |= src & Dj::out & Dl::in & lshc<-(Dj::sh_out + Dl::sh_in)>(target_word(a0, a1, 1 + 2 * j + si));
+          k2 |= src & Dj::in & Dl::out & lshc<-(Dj::sh_in + Dl::sh_out)>(target_word(a0, a1, 1 + 2 * l + ri));
+          k2 |= src & Dj::out & Dl::out &
+                lshc<-(Dj::sh_out + Dl::sh_out)>(target_word(a0, a1, 1 + 2 * N + 4 * pair + 2 * si + ri));
+        });
+      });
       keep |= k2 & below;
     }
     if (lane == 0) d.mask[b] = keep;
@@ -1291,34 +1406,5 @@ struct Ops {
     return &t;
   }
 };
-
-template <int N, int MODEL>
-static const KernelTable* pick(int precision) {
-  return precision == 0 ? Ops<N, MODEL, double>::table(0) : Ops<N, MODEL, float>::table(1);
-}
-
-const KernelTable* kernel_table(int model, int n, int precision) {
-  if (model == kModelL63) return n == 3 ? pick<3, kModelL63>(precision) : nullptr;
-  if (model == kModelL96) {
-    switch (n) {
-      case 4: return pick<4, kModelL96>(precision);
-      case 5: return pick<5, kModelL96>(precision);
-      case 6: return pick<6, kModelL96>(precision);
-      default: return nullptr;
-    }
-  }
-  if (model == kModelLinear) {
-    switch (n) {
-      case 1: return pick<1, kModelLinear>(precision);
-      case 2: return pick<2, kModelLinear>(precision);
-      case 3: return pick<3, kModelLinear>(precision);
-      case 4: return pick<4, kModelLinear>(precision);
-      case 5: return pick<5, kModelLinear>(precision);
-      case 6: return pick<6, kModelLinear>(precision);
-      default: return nullptr;
-    }
-  }
-  return nullptr;
-}
 
 }  // namespace gbees
