@@ -95,6 +95,8 @@ def main():
     ap.add_argument("--max-cells", type=int, default=64 * 8_000_000)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="also run one plain device copy of this many bytes (for counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -112,12 +114,19 @@ def main():
     n = cfg["n"]
     real_size = 4 if cfg.get("precision", 0) == 1 else 8
 
+    if args.calibrate_copy:
+        src = torch.ones(args.calibrate_copy, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     for _ in range(args.warmup):
         run_job(G, cfg, args.max_cells, profile=False)
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    totals = {"cell_updates": 0, "brick_updates": 0, "steps": 0}
+    totals = {"cell_updates": 0, "brick_updates": 0, "steps": 0, "grow_bricks": 0, "inserted": 0}
     prof_sum = {}
     last = None
     for _ in range(args.steps):
@@ -165,6 +174,8 @@ def main():
             "cells_final": last["cells"],
             "bricks_per_step_mean": bricks_per_launch,
             "brick_occupancy": cells_per_step / (64 * bricks_per_launch),
+            "grow_bricks_per_step": totals["grow_bricks"] / max(totals["steps"], 1),
+            "cells_inserted_per_step": totals["inserted"] / max(totals["steps"], 1),
             "parallelism": "single GPU",
         },
         "roofline": {

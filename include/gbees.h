@@ -86,6 +86,8 @@ typedef struct {
   int64_t cells;         /* cells in the grid */
   int64_t bricks;        /* bricks in use */
   int64_t prunes;        /* prune passes run */
+  int64_t grow_bricks;   /* bricks the grow pass expanded (cells newly above threshold since the last prune) */
+  int64_t inserted;      /* cells created by grow */
 } gbees_stats;
 
 /* Device bytes the arena must hold for cfg (0 if cfg is invalid). */

@@ -64,8 +64,11 @@ bool make_layout(const gbees_config& c, Layout* L) {
   L->hcap = h;
   L->ndef = L->cap_b;
   L->real_size = c.precision == 1 ? 4 : 8;
-  L->qbytes = static_cast<size_t>(L->cap_b) * gbees::kLanes * std::max<size_t>(c.n * L->real_size, 32);
-  const size_t cb = L->cap_b;
+  // Q also serves as scratch: the prune-time radix sort needs 48 B per brick plus
+  // a 256 x 256 histogram; marginals need 32 B per table slot.
+  L->qbytes = std::max((static_cast<size_t>(L->cap_b) + 1) * gbees::kLanes * std::max<size_t>(c.n * L->real_size, 32),
+                       static_cast<size_t>(L->cap_b) * 48 + (size_t(1) << 20));
+  const size_t cb = static_cast<size_t>(L->cap_b) + 1;  // + the permanently empty brick at index cap_b
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t at = o;
@@ -629,6 +632,8 @@ int gbees_get_stats(gbees_ctx* c, gbees_stats* out) {
     out->cells = static_cast<int64_t>(c->hsb.cells);
     out->bricks = static_cast<int64_t>(std::min<uint32_t>(c->hsb.nb, c->L.cap_b));
     out->prunes = static_cast<int64_t>(c->hsb.prunes);
+    out->grow_bricks = static_cast<int64_t>(c->hsb.grow_bricks);
+    out->inserted = static_cast<int64_t>(c->hsb.inserted);
   }
   return c->status;
 }

@@ -158,7 +158,7 @@ struct Scalars {
   uint32_t ndeferred;     // grow records whose brick was published by another wave
   int32_t status;
   uint32_t overflow;      // scratch-table overflow of the last marginal call
-  u64 steps, cell_updates, brick_updates, cells, prunes, inserted;
+  u64 steps, cell_updates, brick_updates, cells, prunes, inserted, grow_bricks;
 };
 
 // ---------------------------------------------------------------------------
@@ -180,14 +180,16 @@ struct Dev {
   uint32_t ndef_cap;
   uint64_t hmask;
   // arrays
-  u64* key;            // [cap_b]
-  u64* mask;           // [cap_b]
-  u64* done;           // [cap_b] cells whose grow candidates are known to be present
-  u64* abv;            // [cap_b] above-threshold lanes (prune)
-  uint32_t* nbr;       // [2n][cap_b]; entry 2j is the -e_j neighbour, 2j+1 the +e_j neighbour
-  Real* P0;            // [cap_b * 64]
-  Real* P1;            // [cap_b * 64]
-  Real* Q;             // [cap_b * n * 64]; also scratch for compaction
+  // Brick arrays hold cap_b + 1 bricks: index cap_b is a permanently empty brick
+  // (mask 0, densities 0) that flux passes read in place of a missing neighbour.
+  u64* key;            // [cap_b + 1]
+  u64* mask;           // [cap_b + 1]
+  u64* done;           // [cap_b + 1] cells whose grow candidates are known to be present
+  u64* abv;            // [cap_b + 1] above-threshold lanes (prune)
+  uint32_t* nbr;       // [2n][cap_b + 1]; entry 2j is the -e_j neighbour, 2j+1 the +e_j neighbour
+  Real* P0;            // [(cap_b + 1) * 64]
+  Real* P1;            // [(cap_b + 1) * 64]
+  Real* Q;             // [(cap_b + 1) * n * 64]; also scratch for reordering and marginals
   u64* hkey;           // [hmask + 1]
   uint32_t* hval;      // [hmask + 1]
   u64* defer;          // [ndef_cap * 2]: hash slot, lane bits
@@ -261,12 +263,13 @@ __device__ inline void set_status(Scalars* sb, int32_t code) { atomicCAS(&sb->st
 // ---------------------------------------------------------------------------
 // Hashtable (open addressing, linear probing; Sec. 4.2).
 // ---------------------------------------------------------------------------
+// Lookup; used only by kernels that run after the table was built (plain loads).
 template <typename Real>
 __device__ inline uint32_t hash_find(const Dev<Real>& d, u64 key) {
   u64 h = mix64(key) & d.hmask;
   for (uint64_t probe = 0; probe <= d.hmask; ++probe) {
-    const u64 k = __hip_atomic_load(&d.hkey[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (k == key) return __hip_atomic_load(&d.hval[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const u64 k = d.hkey[h];
+    if (k == key) return d.hval[h];
     if (k == kEmptyKey) return kNone;
     h = (h + 1) & d.hmask;
   }
@@ -280,7 +283,8 @@ __device__ inline u64 hash_claim(const Dev<Real>& d, u64 key, bool* won) {
   u64 h = mix64(key) & d.hmask;
   *won = false;
   for (uint64_t probe = 0; probe <= d.hmask; ++probe) {
-    u64 k = __hip_atomic_load(&d.hkey[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // A stale EMPTY only sends us to the CAS, which is authoritative.
+    u64 k = d.hkey[h];
     if (k == kEmptyKey) {
       u64 expect = kEmptyKey;
       const bool ok = __hip_atomic_compare_exchange_strong(&d.hkey[h], &expect, key, __ATOMIC_RELAXED,
@@ -344,6 +348,25 @@ __device__ __forceinline__ double face_vel(const Dev<Real>& d, const double* xc,
 template <int MODEL, int N, typename Real>
 __device__ __forceinline__ double face_vel_fwd(const Dev<Real>& d, const double* xc, const int32_t* ii, int j) {
   return drift_at<MODEL, N>(xc, j, face_coord(d.mean[j], ii[j] + 1, d.h[j]), d.params);
+}
+
+// Flux-pass velocities at the backward and forward j-faces of a cell with centre xc.
+// Each model's f_j is affine in x_j, so the forward value is the backward one plus
+// (df_j/dx_j) h_j.  Equal to face_vel / face_vel_fwd up to rounding, and used only
+// inside the flux sums, which are continuous in u; the grow and prune decisions and
+// the CFL speed use the exact forms.
+template <int MODEL, int N, typename Real>
+__device__ __forceinline__ void flux_vels(const Dev<Real>& d, const double* xc, int j, double* ub, double* uf) {
+  const double* p = d.params;
+  *ub = drift_at<MODEL, N>(xc, j, xc[j] - 0.5 * d.h[j], p);
+  double dfdx;
+  if constexpr (MODEL == kModelL63)
+    dfdx = j == 0 ? -p[0] : (j == 1 ? -1.0 : -p[2]);
+  else if constexpr (MODEL == kModelL96)
+    dfdx = -1.0;
+  else
+    dfdx = p[j * N + j];
+  *uf = *ub + dfdx * d.h[j];
 }
 
 // S_i = sum_j |f_{i - 1/2 e_j, j}| / h_j (Eq. 8).

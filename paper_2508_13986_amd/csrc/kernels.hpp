@@ -31,7 +31,8 @@
 
 namespace gbees {
 
-// Minimum resident waves per SIMD requested for the flux passes (caps VGPRs).
+// Minimum resident waves per SIMD requested for the flux passes (caps VGPRs;
+// the FP64 flux-B pass holds 5n neighbour values in flight and takes one wave less).
 constexpr int kFluxWavesPerEU = 4;
 
 // ---------------------------------------------------------------------------
@@ -74,8 +75,32 @@ __device__ __forceinline__ bool neighbour_present(u64 mown, u64 mother, int lane
   return ((own ? mown : mother) >> rot_lane<N>(lane, j, d)) & 1ull;
 }
 
+// Exchange with lane ^ STRIDE: DPP quad permutes for strides 1 and 2,
+// ds_swizzle (bit-mask mode, within 32 lanes) for 4..16, a permute for 32.
+template <int STRIDE>
+__device__ __forceinline__ int xor_lane32(int v) {
+  if constexpr (STRIDE == 1)
+    return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+  else if constexpr (STRIDE == 2)
+    return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+  else if constexpr (STRIDE < 32)
+    return __builtin_amdgcn_ds_swizzle(v, (STRIDE << 10) | 0x1F);
+  else
+    return __shfl_xor(v, STRIDE);
+}
+template <int STRIDE>
+__device__ __forceinline__ double xor_shfl(double v) {
+  const int lo = xor_lane32<STRIDE>(__double2loint(v));
+  const int hi = xor_lane32<STRIDE>(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+template <int STRIDE>
+__device__ __forceinline__ float xor_shfl(float v) {
+  return __int_as_float(xor_lane32<STRIDE>(__float_as_int(v)));
+}
+
 // Compile-time-direction variants: J and Dd known, so the offer test is a bit
-// test and 2-wide dimensions use an XOR shuffle.
+// test and 2-wide dimensions use an XOR exchange.
 template <int N, int J, int Dd, typename T>
 __device__ __forceinline__ T nbval(T own, T other, int lane) {
   constexpr int side = brick_side(N, J), stride = brick_stride(N, J);
@@ -84,7 +109,7 @@ __device__ __forceinline__ T nbval(T own, T other, int lane) {
   } else {
     const T offer = offers_own<N>(lane, J, Dd) ? own : other;
     if constexpr (side == 2)
-      return __shfl_xor(offer, stride);
+      return xor_shfl<stride>(offer);
     else
       return __shfl(offer, rot_lane<N>(lane, J, Dd));
   }
@@ -98,17 +123,15 @@ __device__ __forceinline__ bool nbpresent(u64 mown, u64 mother, int lane) {
 }
 
 // MC-limited high-resolution flux correction (LeVeque 2002, ch. 6) of one face:
-// 1/2 |u| (1 - dt |u| / h) phi(theta) W in division-free form.
+// 1/2 |u| (1 - dt |u| / h) phi(theta) W.  For W, W_up of one sign,
+// phi(theta) W = sign(W) min((|W| + |W_up|) / 2, 2 min(|W|, |W_up|)); else 0.
 template <typename Real>
 __device__ __forceinline__ Real hr_term(Real u, Real dth, Real w, Real wup) {
-  if (w * wup <= Real(0)) return Real(0);
-  const Real au = u < Real(0) ? -u : u;
-  const Real aw = w < Real(0) ? -w : w, awu = wup < Real(0) ? -wup : wup;
-  const Real s = w + wup;
-  const Real as = s < Real(0) ? -s : s;
-  Real lim = fmin(as * Real(0.5), fmin(Real(2) * aw, Real(2) * awu));
-  lim = w > Real(0) ? lim : -lim;
-  return Real(0.5) * au * (Real(1) - dth * au) * lim;
+  const Real aw = fabs(w), awu = fabs(wup);
+  const Real lim = fmin(Real(0.5) * (aw + awu), Real(2) * fmin(aw, awu));
+  const Real au = fabs(u);
+  const Real k = Real(0.5) * au * (Real(1) - dth * au);
+  return (w * wup > Real(0)) ? k * copysign(lim, w) : Real(0);
 }
 
 // Workgroup reduction of (max, sum, count) into dpart[blockIdx] (fixed order).
@@ -219,6 +242,7 @@ __global__ void k_scalar(Dev<Real> d, int op, double arg) {
       if (sb->prun) {
         sb->smax_bits = 0ull;
         sb->nb_prev = sb->nb;
+        sb->nb_new = 0;
       }
       break;
     case kOpPruneCommit:
@@ -584,7 +608,8 @@ static __global__ void k_scan(uint32_t* part, uint32_t G, Scalars* sb, int gate,
 // Adds the cells `bits` to the brick with coordinates TB (index tb, or kNone if
 // unknown).  Returns the largest S of the cells this call created (wave-uniform).
 template <int N, int MODEL, typename Real>
-__device__ __forceinline__ double add_cells(const Dev<Real>& d, const int64_t* TB, uint32_t tb, u64 bits, int lane) {
+__device__ __forceinline__ double add_cells(const Dev<Real>& d, const int64_t* TB, uint32_t tb, u64 bits, int lane,
+                                            u64* created_count) {
   if (tb == kNone) {
     if (!brick_in_range<N>(TB)) {
       if (lane == 0) set_status(d.sb, kErrRange);
@@ -636,16 +661,15 @@ __device__ __forceinline__ double add_cells(const Dev<Real>& d, const int64_t* T
       tb = v;
     }
   }
-  u64 cur = 0;
-  if (lane == 0) cur = __hip_atomic_load(&d.mask[tb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  cur = __shfl(cur, 0);
+  // A stale (smaller) mask only costs an extra atomicOr.
+  const u64 cur = d.mask[tb];
   if ((bits & ~cur) == 0ull) return 0.0;
   u64 old = 0;
   if (lane == 0) old = atomicOr(&d.mask[tb], bits);
   old = __shfl(old, 0);
   const u64 created = bits & ~old;
   if (created == 0ull) return 0.0;
-  if (lane == 0) atomicAdd(&d.sb->inserted, static_cast<u64>(__popcll(created)));
+  *created_count += static_cast<u64>(__popcll(created));
   double s = 0.0;
   if ((created >> lane) & 1ull) {
     int32_t ii[N];
@@ -733,16 +757,21 @@ __global__ __launch_bounds__(kWG) void k_grow(Dev<Real> d) {
   __shared__ u64 tbl_all[kWavesPerWG][128];
   u64* tbl = tbl_all[threadIdx.x >> 6];
   double smax = 0.0;
+  u64 nscan = 0, ncreated = 0;
   const WaveRange rg = wave_range(nb_old);
   for (uint32_t b = rg.begin; b < rg.end; b += rg.step) {
-    const u64 m = __hip_atomic_load(&d.mask[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // A stale mask is harmless here: cells added concurrently hold P = 0 and are no sources.
+    const u64 m = d.mask[b];
     const Real p0 = P[static_cast<size_t>(b) * kLanes + lane];
     const bool src = ((m >> lane) & 1ull) && (thr0 ? (p0 != Real(0)) : (p0 >= pstar));
     const u64 S = ballot(src);
     const u64 dn = d.done[b];
     const u64 todo = S & ~dn;
     if (todo == 0ull) continue;
-    if (lane == 0) d.done[b] = dn | S;
+    if (lane == 0) {
+      d.done[b] = dn | S;
+      ++nscan;
+    }
 
     int64_t B[N];
     unpack_key<N>(d.key[b], B);
@@ -815,11 +844,11 @@ __global__ __launch_bounds__(kWG) void k_grow(Dev<Real> d) {
     u64 need0 = 0ull, need1 = 0ull;
     if (bits0 != 0ull) {
       t0 = resolve_target<N>(d, b, lane);
-      need0 = bits0 & ~(t0 != kNone ? __hip_atomic_load(&d.mask[t0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull);
+      need0 = bits0 & ~(t0 != kNone ? d.mask[t0] : 0ull);
     }
     if (bits1 != 0ull) {
       t1 = resolve_target<N>(d, b, lane + 64);
-      need1 = bits1 & ~(t1 != kNone ? __hip_atomic_load(&d.mask[t1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull);
+      need1 = bits1 & ~(t1 != kNone ? d.mask[t1] : 0ull);
     }
     u64 todo_t[2] = {ballot(need0 != 0ull), ballot(need1 != 0ull)};
 #pragma unroll
@@ -837,11 +866,13 @@ __global__ __launch_bounds__(kWG) void k_grow(Dev<Real> d) {
         for (int q = 0; q < N; ++q) TB[q] = B[q];
         if (kind >= 1) TB[j] += s;
         if (kind == 2) TB[l] += r;
-        smax = fmax(smax, add_cells<N, MODEL>(d, TB, tk, bits, lane));
+        smax = fmax(smax, add_cells<N, MODEL>(d, TB, tk, bits, lane, &ncreated));
       }
     }
   }
   if (lane == 0 && smax > 0.0) atomicMax(&sb->smax_bits, double_to_bits(smax));
+  if (lane == 0 && nscan > 0) atomicAdd(&sb->grow_bricks, nscan);
+  if (lane == 0 && ncreated > 0) atomicAdd(&sb->inserted, ncreated);
 }
 
 // Link the bricks created this step and finish inserts that found their brick unpublished.
@@ -854,6 +885,7 @@ __global__ __launch_bounds__(kWG) void k_grow_fix(Dev<Real> d) {
   const uint32_t ndef = min(sb->ndeferred, d.ndef_cap);
   const int lane = lane_id();
   double smax = 0.0;
+  u64 ncreated = 0;
   const uint32_t wid = blockIdx.x * kWavesPerWG + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t nw = gridDim.x * kWavesPerWG;
   for (uint32_t k = wid; k < ndef; k += nw) {
@@ -863,14 +895,19 @@ __global__ __launch_bounds__(kWG) void k_grow_fix(Dev<Real> d) {
     if (tb == kNone || tb >= d.cap_b) continue;
     int64_t TB[N];
     unpack_key<N>(d.key[tb], TB);
-    smax = fmax(smax, add_cells<N, MODEL>(d, TB, tb, bits, lane));
+    smax = fmax(smax, add_cells<N, MODEL>(d, TB, tb, bits, lane, &ncreated));
   }
   if (lane == 0 && smax > 0.0) atomicMax(&sb->smax_bits, double_to_bits(smax));
+  if (lane == 0 && ncreated > 0) atomicAdd(&sb->inserted, ncreated);
 }
 
 // ---------------------------------------------------------------------------
 // Flux pass A: transverse fluctuations and corrected states Q_l
 // ---------------------------------------------------------------------------
+// Both flux passes load in three phases so the memory round trips overlap:
+// (1) every axis-neighbour brick index, (2) every neighbour row, issued
+// unconditionally (a missing neighbour reads the brick's own row and is zeroed
+// afterwards, so no branch splits the loads), (3) the arithmetic.
 template <int N, int MODEL, typename Real>
 __global__ __launch_bounds__(kWG, kFluxWavesPerEU) void k_flux_a(Dev<Real> d) {
   const Scalars* sb = d.sb;
@@ -882,30 +919,45 @@ __global__ __launch_bounds__(kWG, kFluxWavesPerEU) void k_flux_a(Dev<Real> d) {
 #pragma unroll
   for (int j = 0; j < N; ++j) c[j] = static_cast<Real>(dt / (2.0 * d.h[j]));
   const int lane = lane_id();
+  double xoff[N];  // this lane's offset from its brick's corner cell centre
+#pragma unroll
+  for (int j = 0; j < N; ++j) xoff[j] = static_cast<double>((lane >> brick_off(N, j)) & (brick_side(N, j) - 1)) * d.h[j];
   const WaveRange rg = wave_range(nb);
   for (uint32_t b = rg.begin; b < rg.end; b += rg.step) {
+    uint32_t bm[N], bp[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      bm[j] = nbr_of(d, b, j, -1);
+      bp[j] = nbr_of(d, b, j, 1);
+    }
     const u64 m = d.mask[b];
-    int64_t B[N];
-    unpack_key<N>(d.key[b], B);
-    int32_t ii[N];
-    double xc[N];
-    cell_of<N>(d, B, lane, ii, xc);
-    const bool act = (m >> lane) & 1ull;
+    const u64 key = d.key[b];
     const Real p0 = P[static_cast<size_t>(b) * kLanes + lane];
+    // Missing neighbours read the permanently empty brick at index cap_b.
+    Real Pm[N], Pp[N];
+    u64 mp[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const uint32_t im = bm[j] != kNone ? bm[j] : d.cap_b, ip = bp[j] != kNone ? bp[j] : d.cap_b;
+      Pm[j] = P[static_cast<size_t>(im) * kLanes + lane];
+      Pp[j] = P[static_cast<size_t>(ip) * kLanes + lane];
+      mp[j] = d.mask[ip];
+    }
+    int64_t B[N];
+    unpack_key<N>(key, B);
+    double xc[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) xc[j] = (d.mean[j] + static_cast<double>(B[j] * brick_side(N, j)) * d.h[j]) + xoff[j];
+    const bool act = (m >> lane) & 1ull;
     Real T[N];
     static_for<N>([&](auto Jc) {
       constexpr int j = decltype(Jc)::value;
-      const uint32_t bm = nbr_of(d, b, j, -1), bp = nbr_of(d, b, j, 1);
-      const Real* Pmb = P + static_cast<size_t>(bm) * kLanes;
-      const Real* Ppb = P + static_cast<size_t>(bp) * kLanes;
-      const Real Pm = bm != kNone ? Pmb[lane] : Real(0);
-      const Real Pp = bp != kNone ? Ppb[lane] : Real(0);
-      const u64 mp = bp != kNone ? d.mask[bp] : 0ull;
-      const Real pm = nbval<N, j, -1>(p0, Pm, lane);
-      const Real pp = nbval<N, j, 1>(p0, Pp, lane);
-      const bool ep = nbpresent<N, j, 1>(m, mp, lane);
-      const Real ub = static_cast<Real>(face_vel<MODEL, N>(d, xc, ii, j));
-      const Real uf = static_cast<Real>(face_vel_fwd<MODEL, N>(d, xc, ii, j));
+      const Real pm = nbval<N, j, -1>(p0, Pm[j], lane);
+      const Real pp = nbval<N, j, 1>(p0, Pp[j], lane);
+      const bool ep = nbpresent<N, j, 1>(m, mp[j], lane);
+      double ubd, ufd;
+      flux_vels<MODEL, N>(d, xc, j, &ubd, &ufd);
+      const Real ub = static_cast<Real>(ubd), uf = static_cast<Real>(ufd);
       T[j] = rpos(ub) * (p0 - pm) + (ep ? rneg(uf) * (pp - p0) : Real(0));
     });
     Real* Qb = d.Q + static_cast<size_t>(b) * N * kLanes + lane;
@@ -924,7 +976,7 @@ __global__ __launch_bounds__(kWG, kFluxWavesPerEU) void k_flux_a(Dev<Real> d) {
 // Flux pass B: face fluxes, high-resolution term, conservative update
 // ---------------------------------------------------------------------------
 template <int N, int MODEL, typename Real>
-__global__ __launch_bounds__(kWG, kFluxWavesPerEU) void k_flux_b(Dev<Real> d) {
+__global__ __launch_bounds__(kWG, sizeof(Real) == 8 ? kFluxWavesPerEU - 1 : kFluxWavesPerEU) void k_flux_b(Dev<Real> d) {
   const Scalars* sb = d.sb;
   if (!sb->run) return;
   const uint32_t nb = nb_of(d);
@@ -936,45 +988,62 @@ __global__ __launch_bounds__(kWG, kFluxWavesPerEU) void k_flux_b(Dev<Real> d) {
   for (int j = 0; j < N; ++j) dth[j] = static_cast<Real>(dt / d.h[j]);
   const bool hr = d.limiter != 0;
   const int lane = lane_id();
+  double xoff[N];  // this lane's offset from its brick's corner cell centre
+#pragma unroll
+  for (int j = 0; j < N; ++j) xoff[j] = static_cast<double>((lane >> brick_off(N, j)) & (brick_side(N, j) - 1)) * d.h[j];
   double vmax = 0.0, vsum = 0.0, vcnt = 0.0;
   const WaveRange rg = wave_range(nb);
   for (uint32_t b = rg.begin; b < rg.end; b += rg.step) {
+    uint32_t bm[N], bp[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      bm[j] = nbr_of(d, b, j, -1);
+      bp[j] = nbr_of(d, b, j, 1);
+    }
     const u64 m = d.mask[b];
-    int64_t B[N];
-    unpack_key<N>(d.key[b], B);
-    int32_t ii[N];
-    double xc[N];
-    cell_of<N>(d, B, lane, ii, xc);
-    const bool act = (m >> lane) & 1ull;
+    const u64 key = d.key[b];
     const size_t o = static_cast<size_t>(b) * kLanes + lane;
     const Real p0 = P[o];
     const Real* Qb = d.Q + static_cast<size_t>(b) * N * kLanes;
+    Real Pm[N], Pp[N], Qm[N], Qp[N], q[N];
+    u64 mm[N], mp[N];
+    // Missing neighbours read the permanently empty brick at index cap_b: its
+    // densities and mask are zero; its Q row is never used (no face to it).
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      const uint32_t im = bm[l] != kNone ? bm[l] : d.cap_b, ip = bp[l] != kNone ? bp[l] : d.cap_b;
+      Pm[l] = P[static_cast<size_t>(im) * kLanes + lane];
+      Pp[l] = P[static_cast<size_t>(ip) * kLanes + lane];
+      Qm[l] = d.Q[(static_cast<size_t>(im) * N + l) * kLanes + lane];
+      Qp[l] = d.Q[(static_cast<size_t>(ip) * N + l) * kLanes + lane];
+      q[l] = Qb[l * kLanes + lane];
+      mm[l] = d.mask[im];
+      mp[l] = d.mask[ip];
+    }
+    int64_t B[N];
+    unpack_key<N>(key, B);
+    double xc[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) xc[j] = (d.mean[j] + static_cast<double>(B[j] * brick_side(N, j)) * d.h[j]) + xoff[j];
+    const bool act = (m >> lane) & 1ull;
     Real acc = p0;
     static_for<N>([&](auto Lc) {
       constexpr int l = decltype(Lc)::value;
-      const uint32_t bm = nbr_of(d, b, l, -1), bp = nbr_of(d, b, l, 1);
-      const Real* Pmb = P + static_cast<size_t>(bm) * kLanes;
-      const Real* Ppb = P + static_cast<size_t>(bp) * kLanes;
-      const Real* Qmb = d.Q + (static_cast<size_t>(bm) * N + l) * kLanes;
-      const Real* Qpb = d.Q + (static_cast<size_t>(bp) * N + l) * kLanes;
-      const Real Pm = bm != kNone ? Pmb[lane] : Real(0);
-      const Real Pp = bp != kNone ? Ppb[lane] : Real(0);
-      const Real Qm = bm != kNone ? Qmb[lane] : Real(0);
-      const Real Qp = bp != kNone ? Qpb[lane] : Real(0);
-      const u64 mm = bm != kNone ? d.mask[bm] : 0ull, mp = bp != kNone ? d.mask[bp] : 0ull;
-      const Real q = Qb[l * kLanes + lane];
-      const bool em = nbpresent<N, l, -1>(m, mm, lane), ep = nbpresent<N, l, 1>(m, mp, lane);
-      const Real pm1 = nbval<N, l, -1>(p0, Pm, lane);
-      const Real pp1 = nbval<N, l, 1>(p0, Pp, lane);
-      const Real qm = nbval<N, l, -1>(q, Qm, lane);
-      const Real qp = nbval<N, l, 1>(q, Qp, lane);
-      const Real ub = static_cast<Real>(face_vel<MODEL, N>(d, xc, ii, l));
-      const Real uf = static_cast<Real>(face_vel_fwd<MODEL, N>(d, xc, ii, l));
-      Real fb = rpos(ub) * qm + rneg(ub) * q;
-      Real ff = rpos(uf) * q + rneg(uf) * qp;
+      const Real vPm = Pm[l], vPp = Pp[l];
+      const bool em = nbpresent<N, l, -1>(m, mm[l], lane);
+      const bool ep = nbpresent<N, l, 1>(m, mp[l], lane);
+      const Real pm1 = nbval<N, l, -1>(p0, vPm, lane);
+      const Real pp1 = nbval<N, l, 1>(p0, vPp, lane);
+      const Real qm = nbval<N, l, -1>(q[l], Qm[l], lane);
+      const Real qp = nbval<N, l, 1>(q[l], Qp[l], lane);
+      double ubd, ufd;
+      flux_vels<MODEL, N>(d, xc, l, &ubd, &ufd);
+      const Real ub = static_cast<Real>(ubd), uf = static_cast<Real>(ufd);
+      Real fb = rpos(ub) * qm + rneg(ub) * q[l];
+      Real ff = rpos(uf) * q[l] + rneg(uf) * qp;
       if (hr) {
-        const Real pm2 = nbval<N, l, -2>(p0, Pm, lane);
-        const Real pp2 = nbval<N, l, 2>(p0, Pp, lane);
+        const Real pm2 = nbval<N, l, -2>(p0, vPm, lane);
+        const Real pp2 = nbval<N, l, 2>(p0, vPp, lane);
         fb += hr_term(ub, dth[l], p0 - pm1, ub > Real(0) ? pm1 - pm2 : pp1 - p0);
         ff += hr_term(uf, dth[l], pp1 - p0, uf > Real(0) ? p0 - pm1 : pp2 - pp1);
       }
@@ -1099,68 +1168,179 @@ __global__ __launch_bounds__(kWG) void k_prune_mark(Dev<Real> d) {
   if (lane == 0 && smax > 0.0) atomicMax(&sb->smax_bits, double_to_bits(smax));
 }
 
-// Stable compaction of the bricks that kept at least one cell.
+// ---------------------------------------------------------------------------
+// Reordering at prune: the bricks that kept a cell are sorted by the Morton
+// code of their brick coordinates (removed bricks sort last), so that the
+// axis neighbours of a brick sit close to it in memory and in time.  Stable
+// LSD radix sort, 8-bit digits, one digit histogram per workgroup chunk.
+// Scratch (in the Q region): keys A/B, values A/B, then key2/mask2 copies.
+// ---------------------------------------------------------------------------
+constexpr int kSortWG = 256;  // workgroups of the radix passes (chunked)
+
+struct SortScratch {
+  u64 *ka, *kb;
+  uint32_t *va, *vb;
+  u64 *key2, *mask2;
+  uint32_t* hist;  // [256][kSortWG]
+};
 template <typename Real>
-__global__ __launch_bounds__(kWG) void k_compact_count(Dev<Real> d) {
-  if (!d.sb->prun) return;
+__device__ __forceinline__ SortScratch sort_scratch(const Dev<Real>& d) {
+  const size_t cap = d.cap_b;
+  u64* base = reinterpret_cast<u64*>(d.Q);
+  SortScratch sc;
+  sc.ka = base;
+  sc.kb = base + cap;
+  sc.key2 = base + 2 * cap;
+  sc.mask2 = base + 3 * cap;
+  sc.va = reinterpret_cast<uint32_t*>(base + 4 * cap);
+  sc.vb = sc.va + cap;
+  sc.hist = sc.vb + cap;
+  return sc;
+}
+
+template <int N>
+__device__ __forceinline__ u64 morton_code(const int64_t* B) {
+  u64 code = 0;
+  constexpr int kb = key_bits(N) < 10 ? key_bits(N) : 10;  // 10 bits per coordinate suffice (|B| < 512)
+#pragma unroll
+  for (int bit = 0; bit < kb; ++bit)
+#pragma unroll
+    for (int j = 0; j < N; ++j) code |= static_cast<u64>(((B[j] + 512) >> bit) & 1) << (bit * N + j);
+  return code;
+}
+
+// Sort keys of all bricks in [0, nb_prev): Morton code of survivors, ~0 for removed bricks.
+template <int N, typename Real>
+__global__ __launch_bounds__(kWG) void k_sort_keys(Dev<Real> d, int gate) {
+  if (!gate_open(d, gate)) return;
+  const SortScratch sc = sort_scratch(d);
+  const uint32_t nb = min(d.sb->nb_prev, d.cap_b);
+  uint32_t kept = 0;
+  for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += gridDim.x * blockDim.x) {
+    int64_t B[N];
+    unpack_key<N>(d.key[b], B);
+    const bool alive = d.mask[b] != 0ull;
+    sc.ka[b] = alive ? morton_code<N>(B) : ~0ull;
+    sc.va[b] = b;
+    kept += alive ? 1u : 0u;
+  }
+  for (int o = 32; o > 0; o >>= 1) kept += __shfl_xor(kept, o);
+  if (lane_id() == 0 && kept) atomicAdd(&d.sb->nb_new, kept);
+}
+
+// Per-chunk histogram of digit `shift`.
+template <typename Real>
+__global__ __launch_bounds__(kWG) void k_sort_hist(Dev<Real> d, int gate, int shift, int flip) {
+  if (!gate_open(d, gate)) return;
+  const SortScratch sc = sort_scratch(d);
+  const u64* keys = flip ? sc.kb : sc.ka;
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
   uint64_t lo, hi;
   wg_chunk(min(d.sb->nb_prev, d.cap_b), lo, hi);
-  uint32_t cnt = 0;
-  for (uint64_t b = lo + threadIdx.x; b < hi; b += blockDim.x) cnt += (d.mask[b] != 0ull) ? 1u : 0u;
-  __shared__ uint32_t sh[kWG];
-  sh[threadIdx.x] = cnt;
+  for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+  __syncthreads();
+  sc.hist[threadIdx.x * kSortWG + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive scan of the digit-major histogram (256 x kSortWG entries).
+template <typename Real>
+__global__ __launch_bounds__(kWG) void k_sort_scan(Dev<Real> d, int gate) {
+  if (!gate_open(d, gate)) return;
+  const SortScratch sc = sort_scratch(d);
+  __shared__ uint32_t tot[kWG];
+  uint32_t* row = sc.hist + threadIdx.x * kSortWG;  // thread t owns digit t
+  uint32_t s = 0;
+  for (int w = 0; w < kSortWG; ++w) s += row[w];
+  tot[threadIdx.x] = s;
   __syncthreads();
   if (threadIdx.x == 0) {
-    uint32_t s = 0;
-    for (int k = 0; k < kWG; ++k) s += sh[k];
-    d.part[blockIdx.x] = s;
+    uint32_t acc = 0;
+    for (int k = 0; k < kWG; ++k) {
+      const uint32_t v = tot[k];
+      tot[k] = acc;
+      acc += v;
+    }
+  }
+  __syncthreads();
+  uint32_t acc = tot[threadIdx.x];
+  for (int w = 0; w < kSortWG; ++w) {
+    const uint32_t v = row[w];
+    row[w] = acc;
+    acc += v;
   }
 }
 
+// Stable scatter: elements of a chunk keep their order within each digit.
 template <typename Real>
-__global__ __launch_bounds__(kWG) void k_compact_scatter(Dev<Real> d) {
-  if (!d.sb->prun) return;
+__global__ __launch_bounds__(kWG) void k_sort_scatter(Dev<Real> d, int gate, int shift, int flip) {
+  if (!gate_open(d, gate)) return;
+  const SortScratch sc = sort_scratch(d);
+  const u64* kin = flip ? sc.kb : sc.ka;
+  u64* kout = flip ? sc.ka : sc.kb;
+  const uint32_t* vin = flip ? sc.vb : sc.va;
+  uint32_t* vout = flip ? sc.va : sc.vb;
+  __shared__ uint32_t base[256];
+  __shared__ uint32_t cnt[kWavesPerWG][256];
+  const int lane = lane_id(), w = threadIdx.x >> 6;
+  base[threadIdx.x] = sc.hist[threadIdx.x * kSortWG + blockIdx.x];
   uint64_t lo, hi;
   wg_chunk(min(d.sb->nb_prev, d.cap_b), lo, hi);
+  for (uint64_t r0 = lo; r0 < hi; r0 += kWG) {
+    for (int k = 0; k < kWavesPerWG; ++k) cnt[k][threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t i = r0 + threadIdx.x;
+    const bool valid = i < hi;
+    const u64 key = valid ? kin[i] : 0ull;
+    const uint32_t dig = static_cast<uint32_t>((key >> shift) & 255u);
+    // lanes of this wave holding the same digit (multisplit by 8 ballots)
+    u64 same = ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const u64 bb = ballot(((dig >> bit) & 1u) != 0u);
+      same &= ((dig >> bit) & 1u) ? bb : ~bb;
+    }
+    const uint32_t rank = static_cast<uint32_t>(__popcll(same & ((1ull << lane) - 1ull)));
+    const bool leader = valid && rank == 0;
+    if (leader) cnt[w][dig] = static_cast<uint32_t>(__popcll(same));
+    __syncthreads();
+    if (valid) {
+      uint32_t before = base[dig];
+      for (int k = 0; k < w; ++k) before += cnt[k][dig];
+      const uint32_t dst = before + rank;
+      kout[dst] = key;
+      vout[dst] = vin[i];
+    }
+    __syncthreads();
+    uint32_t add = 0;
+    for (int k = 0; k < kWavesPerWG; ++k) add += cnt[k][threadIdx.x];
+    base[threadIdx.x] += add;
+    __syncthreads();
+  }
+}
+
+// Gather the survivors in sorted order: key/mask into scratch copies, densities
+// into the other buffer with removed lanes cleared.
+template <typename Real>
+__global__ __launch_bounds__(kWG) void k_sort_permute(Dev<Real> d, int gate, int flip) {
+  if (!gate_open(d, gate)) return;
+  const SortScratch sc = sort_scratch(d);
+  const uint32_t* perm = flip ? sc.vb : sc.va;  // result of the last pass
+  const uint32_t nb_new = min(d.sb->nb_new, d.cap_b);
   const Real* P = cur_p(d);
   Real* Pn = next_p(d);
-  u64* key2 = reinterpret_cast<u64*>(d.Q);
-  u64* mask2 = key2 + d.cap_b;
-  const int lane = lane_id(), w = threadIdx.x >> 6;
-  uint32_t base = d.part[blockIdx.x];
-  __shared__ uint32_t shw[kWavesPerWG];
-  __shared__ uint32_t src_b[kWG], dst_b[kWG];
-  __shared__ u64 msk[kWG];
-  for (uint64_t r0 = lo; r0 < hi; r0 += kWG) {
-    const uint64_t b = r0 + threadIdx.x;
-    const u64 m = b < hi ? d.mask[b] : 0ull;
-    const bool f = m != 0ull;
-    const u64 bal = ballot(f);
-    const uint32_t pre = static_cast<uint32_t>(__popcll(bal & ((1ull << lane) - 1ull)));
-    if (lane == 0) shw[w] = static_cast<uint32_t>(__popcll(bal));
-    __syncthreads();
-    uint32_t before = 0, total = 0;
-    for (int k = 0; k < kWavesPerWG; ++k) {
-      before += (k < w) ? shw[k] : 0u;
-      total += shw[k];
+  const int lane = lane_id();
+  const WaveRange rg = wave_range(nb_new);
+  for (uint32_t k = rg.begin; k < rg.end; k += rg.step) {
+    const uint32_t src = perm[k];
+    const u64 m = d.mask[src];
+    if (lane == 0) {
+      sc.key2[k] = d.key[src];
+      sc.mask2[k] = m;
     }
-    const uint32_t dst = base + before + pre;
-    src_b[threadIdx.x] = f ? static_cast<uint32_t>(b) : kNone;
-    dst_b[threadIdx.x] = dst;
-    msk[threadIdx.x] = m;
-    if (f) {
-      key2[dst] = d.key[b];
-      mask2[dst] = m;
-    }
-    __syncthreads();
-    for (int e = w * kLanes; e < (w + 1) * kLanes; ++e) {
-      const uint32_t sbk = src_b[e];
-      if (sbk == kNone) continue;
-      const Real v = P[static_cast<size_t>(sbk) * kLanes + lane];
-      Pn[static_cast<size_t>(dst_b[e]) * kLanes + lane] = ((msk[e] >> lane) & 1ull) ? v : Real(0);
-    }
-    base += total;
-    __syncthreads();
+    const Real v = P[static_cast<size_t>(src) * kLanes + lane];
+    Pn[static_cast<size_t>(k) * kLanes + lane] = ((m >> lane) & 1ull) ? v : Real(0);
   }
 }
 
@@ -1168,14 +1348,13 @@ template <typename Real>
 __global__ __launch_bounds__(kWG) void k_compact_finish(Dev<Real> d) {
   if (!d.sb->prun) return;
   const uint32_t nb_new = min(d.sb->nb_new, d.cap_b), nb_prev = min(d.sb->nb_prev, d.cap_b);
-  const u64* key2 = reinterpret_cast<const u64*>(d.Q);
-  const u64* mask2 = key2 + d.cap_b;
+  const SortScratch sc = sort_scratch(d);
   const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
   const uint64_t tid = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x;
   for (uint64_t b = tid; b < nb_prev; b += stride) {
     if (b < nb_new) {
-      d.key[b] = key2[b];
-      d.mask[b] = mask2[b];
+      d.key[b] = sc.key2[b];
+      d.mask[b] = sc.mask2[b];
     } else {
       d.mask[b] = 0ull;
     }
@@ -1302,6 +1481,18 @@ template <int N, int MODEL, typename Real>
 struct Ops {
   static const Dev<Real>& D(const void* p) { return *static_cast<const Dev<Real>*>(p); }
 
+  // Survivors sorted by Morton code (prune gate); result in the sort scratch.
+  static void reorder(const Dev<Real>& d, hipStream_t s, uint32_t G) {
+    k_sort_keys<N, Real><<<G, kWG, 0, s>>>(d, kGatePrune);
+    int flip = 0;
+    for (int shift = 0; shift < 64; shift += 8, flip ^= 1) {
+      k_sort_hist<Real><<<kSortWG, kWG, 0, s>>>(d, kGatePrune, shift, flip);
+      k_sort_scan<Real><<<1, kWG, 0, s>>>(d, kGatePrune);
+      k_sort_scatter<Real><<<kSortWG, kWG, 0, s>>>(d, kGatePrune, shift, flip);
+    }
+    k_sort_permute<Real><<<G, kWG, 0, s>>>(d, kGatePrune, flip);
+  }
+
   static void rebuild_links(const Dev<Real>& d, hipStream_t s, uint32_t G, int gate) {
     k_hash_clear<Real><<<G, kWG, 0, s>>>(d, gate);
     k_hash_insert_all<Real><<<G, kWG, 0, s>>>(d, gate);
@@ -1360,9 +1551,7 @@ struct Ops {
     k_scalar<Real><<<1, 64, 0, s>>>(d, from_step ? kOpPruneBeginStep : kOpPruneBeginAlways, 0.0);
     k_prune_above<N, Real><<<G, kWG, 0, s>>>(d);
     k_prune_mark<N, MODEL, Real><<<G, kWG, 0, s>>>(d);
-    k_compact_count<Real><<<G, kWG, 0, s>>>(d);
-    k_scan<<<1, kWG, 0, s>>>(d.part, G, d.sb, kGatePrune, &d.sb->nb_new, d.cap_b);
-    k_compact_scatter<Real><<<G, kWG, 0, s>>>(d);
+    reorder(d, s, G);
     k_compact_finish<Real><<<G, kWG, 0, s>>>(d);
     k_scalar<Real><<<1, 64, 0, s>>>(d, kOpPruneCommit, 0.0);
     rebuild_links(d, s, G, kGatePrune);

@@ -51,6 +51,8 @@ class GbeesStats(ctypes.Structure):
         ("cells", ctypes.c_int64),
         ("bricks", ctypes.c_int64),
         ("prunes", ctypes.c_int64),
+        ("grow_bricks", ctypes.c_int64),
+        ("inserted", ctypes.c_int64),
     ]
 
 

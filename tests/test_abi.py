@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layout_matches_header():
     # gbees_config: 2 ints, 48+6+6+36 doubles, 3 doubles, 4 ints, int64, double
     assert ctypes.sizeof(G.GbeesConfig) == 8 + 8 * 96 + 24 + 16 + 8 + 8
-    assert ctypes.sizeof(G.GbeesStats) == 5 * 8 + 6 * 8
+    assert ctypes.sizeof(G.GbeesStats) == 5 * 8 + 8 * 8
 
 
 def test_arena_sizing_and_validation():
