@@ -11,7 +11,6 @@ Prints one JSON line (metric, value, roofline of the dominant kernel measured
 with HIP events on the launch stream, and the CPU oracle on a bounded sample).
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -35,17 +34,10 @@ def flux_a_bytes_per_brick(n, real_size):
     return 64 * real_size + 64 * n * real_size + 8 + 8 + 4 * 2 * n
 
 
-def kernel_source_hash():
-    h = hashlib.sha256()
-    for f in ("gbees_dev.hpp", "kernels.hpp"):
-        with open(os.path.join(ROOT, "paper_2508_13986_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
-def measured_traffic(workload, bricks_per_launch):
-    """HBM bytes per flux-B launch from committed rocprofv3 counter runs, if they
-    were taken on the current kernel source; else None."""
+def pmc_record(workload):
+    """Counter averages for one flux-B launch from the committed rocprofv3 --pmc
+    runs of this workload, if they were taken on the current kernel source."""
+    from paper_2508_13986_amd.profsum import kernel_source_hash
     path = os.path.join(ROOT, "profiles", f"flux_b_{workload}_pmc.json")
     if not os.path.exists(path):
         return None
@@ -53,7 +45,14 @@ def measured_traffic(workload, bricks_per_launch):
         d = json.load(fh)
     if d.get("kernel_source_hash") != kernel_source_hash():
         return None
-    per_brick = (d["fetch_bytes_per_launch"] + d["write_bytes_per_launch"]) / d["bricks_per_launch"]
+    return d
+
+
+def measured_traffic(rec, bricks_per_launch):
+    """HBM bytes per flux-B launch (counter bytes per brick, scaled to this run)."""
+    if rec is None or "fetch_bytes_per_launch" not in rec or "write_bytes_per_launch" not in rec:
+        return None
+    per_brick = (rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]) / rec["bricks_per_launch"]
     return per_brick * bricks_per_launch
 
 
@@ -114,12 +113,13 @@ def main():
     n = cfg["n"]
     real_size = 4 if cfg.get("precision", 0) == 1 else 8
 
-    if args.calibrate_copy:
+    if args.calibrate_copy:  # a plain copy of known size, to scale the HBM byte counters by
         src = torch.ones(args.calibrate_copy, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+        torch.cuda.empty_cache()
 
     for _ in range(args.warmup):
         run_job(G, cfg, args.max_cells, profile=False)
@@ -150,7 +150,9 @@ def main():
     bytes_b = flux_b_bytes_per_brick(n, real_size) * bricks_per_launch
     bytes_a = flux_a_bytes_per_brick(n, real_size) * bricks_per_launch
     achieved = bytes_b / avg_b / 1e9
-    traffic = measured_traffic(args.workload, bricks_per_launch)
+    rec = pmc_record(args.workload)
+    traffic = measured_traffic(rec, bricks_per_launch)
+    valu_busy = rec.get("derived", {}).get("valu_busy_pct") if rec else None
     cells_per_step = totals["cell_updates"] / max(totals["steps"], 1)
     line = {
         "metric": "CTU cell-updates/s (Lorenz-96 6D)",
@@ -186,6 +188,7 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
             "traffic": traffic,
+            "valu_busy_pct": valu_busy,
             "avg_launch_us": avg_b * 1e6,
             "algorithmic_bytes_per_launch": bytes_b,
         },
