@@ -31,9 +31,12 @@
 
 namespace gbees {
 
-// Minimum resident waves per SIMD requested for the flux passes (caps VGPRs;
-// the FP64 flux-B pass holds 5n neighbour values in flight and takes one wave less).
+// Minimum resident waves per SIMD requested for the flux passes (caps VGPRs).
+// The FP64 flux-B pass holds 4n neighbour values in flight plus its own
+// corrected states; it runs fastest at two waves with no spills (measured:
+// 3.8 ms per step on the Lorenz-96 6D grid, 4.6 ms at three waves with spills).
 constexpr int kFluxWavesPerEU = 4;
+constexpr int kFluxBWavesPerEU64 = 2, kFluxBWavesPerEU32 = 3;
 
 // ---------------------------------------------------------------------------
 // Small helpers
@@ -55,25 +58,24 @@ __device__ __forceinline__ int rot_lane(int lane, int j, int d) {
   const int a2 = (a + d + side) & (side - 1);
   return lane + ((a2 - a) << off);
 }
-// Does lane L (coordinate a_j) serve its partner from its own brick?
+// Does lane `lane` serve its partner at distance d along j from its own brick?
 template <int N>
 __device__ __forceinline__ bool offers_own(int lane, int j, int d) {
   const int side = brick_side(N, j);
   const int a = (lane >> brick_off(N, j)) & (side - 1);
   return d > 0 ? (a >= d) : (a < side + d);
 }
-template <int N, typename T>
-__device__ __forceinline__ T neighbour(T own, T other, int lane, int j, int d) {
-  const T offer = offers_own<N>(lane, j, d) ? own : other;
-  return (brick_side(N, j) == 2 && (d == 2 || d == -2)) ? other : __shfl(offer, rot_lane<N>(lane, j, d));
+// The same as a lane mask.
+__host__ __device__ constexpr u64 offer_own_lanes(int n, int j, int d) {
+  u64 m = 0;
+  for (int v = 0; v < brick_side(n, j); ++v)
+    if (d > 0 ? v >= d : v < brick_side(n, j) + d) m |= lanes_at(n, j, v);
+  return m;
 }
-template <int N>
-__device__ __forceinline__ bool neighbour_present(u64 mown, u64 mother, int lane, int j, int d) {
-  const int side = brick_side(N, j);
-  const int a = (lane >> brick_off(N, j)) & (side - 1);
-  const bool own = (a + d >= 0) && (a + d < side);
-  return ((own ? mown : mother) >> rot_lane<N>(lane, j, d)) & 1ull;
-}
+// Per-lane conditions that depend only on the lane's position and on
+// wave-uniform masks are formed as 64-bit lane masks with scalar
+// instructions and used directly as the condition of a select.
+__device__ __forceinline__ bool lane_in(u64 mask) { return __builtin_amdgcn_inverse_ballot_w64(mask); }
 
 // Exchange with lane ^ STRIDE: DPP quad permutes for strides 1 and 2,
 // ds_swizzle (bit-mask mode, within 32 lanes) for 4..16, a permute for 32.
@@ -99,27 +101,29 @@ __device__ __forceinline__ float xor_shfl(float v) {
   return __int_as_float(xor_lane32<STRIDE>(__float_as_int(v)));
 }
 
-// Compile-time-direction variants: J and Dd known, so the offer test is a bit
-// test and 2-wide dimensions use an XOR exchange.
+// Compile-time-direction variants: J and Dd known, so the offer test is a
+// constant lane mask and 2-wide dimensions use an XOR exchange.
 template <int N, int J, int Dd, typename T>
 __device__ __forceinline__ T nbval(T own, T other, int lane) {
   constexpr int side = brick_side(N, J), stride = brick_stride(N, J);
   if constexpr (side == 2 && (Dd == 2 || Dd == -2)) {
     return other;
+  } else if constexpr (side == 2) {
+    return xor_shfl<stride>(lane_in(offer_own_lanes(N, J, Dd)) ? own : other);
   } else {
+    // Wider bricks test the lane's coordinate directly: selecting with the
+    // constant lane mask ahead of the bpermute produced wrong neighbour
+    // values for them (n = 2, 3) in the GPU parity tests.
     const T offer = offers_own<N>(lane, J, Dd) ? own : other;
-    if constexpr (side == 2)
-      return xor_shfl<stride>(offer);
-    else
-      return __shfl(offer, rot_lane<N>(lane, J, Dd));
+    return __shfl(offer, rot_lane<N>(lane, J, Dd));
   }
 }
-template <int N, int J, int Dd>
-__device__ __forceinline__ bool nbpresent(u64 mown, u64 mother, int lane) {
-  constexpr int side = brick_side(N, J), off = brick_off(N, J);
-  const int a = (lane >> off) & (side - 1);
-  const bool own = (a + Dd >= 0) && (a + Dd < side);
-  return ((own ? mown : mother) >> rot_lane<N>(lane, J, Dd)) & 1ull;
+// Lanes whose neighbour at S = +-1 along J is in the grid, given this brick's
+// mask and the mask of the brick at S e_J.
+template <int N, int J, int S>
+__device__ __forceinline__ u64 present_lanes(u64 mown, u64 mother) {
+  using D = Dir<N, J, S>;
+  return (lshc<-D::sh_in>(mown) & D::in) | (lshc<-D::sh_out>(mother) & D::out);
 }
 
 // MC-limited high-resolution flux correction (LeVeque 2002, ch. 6) of one face:
@@ -685,6 +689,42 @@ __device__ __forceinline__ uint32_t nbr_of(const Dev<Real>& d, uint32_t b, int j
   return b == kNone ? kNone : d.nbr[static_cast<size_t>(2 * j + (s > 0 ? 1 : 0)) * d.cap_b + b];
 }
 
+// Per-brick metadata of the flux passes, gathered into one VGPR so that the
+// next brick's links, mask and key can be fetched while the current brick is
+// computed: lane 2j + s holds the link to the brick at (s ? +1 : -1) e_j, lanes
+// 2n, 2n + 1 the occupancy mask and lanes 2n + 2, 2n + 3 the key (low word
+// first).  b == kNone loads nothing.
+template <int N, typename Real>
+__device__ __forceinline__ uint32_t meta_fetch(const Dev<Real>& d, uint32_t b, int lane) {
+  uint32_t v = 0;
+  if (b != kNone && lane < 2 * N + 4) {
+    const uint32_t* src =
+        lane < 2 * N ? d.nbr + static_cast<size_t>(lane) * d.cap_b + b
+                     : (lane < 2 * N + 2 ? reinterpret_cast<const uint32_t*>(d.mask + b) + (lane - 2 * N)
+                                         : reinterpret_cast<const uint32_t*>(d.key + b) + (lane - 2 * N - 2));
+    v = *src;
+  }
+  return v;
+}
+template <int N>
+struct BrickMeta {
+  uint32_t bm[N], bp[N];
+  u64 mask, key;
+};
+template <int N>
+__device__ __forceinline__ BrickMeta<N> meta_unpack(uint32_t v) {
+  BrickMeta<N> r;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    r.bm[j] = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), 2 * j));
+    r.bp[j] = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), 2 * j + 1));
+  }
+  auto word = [&](int k) { return static_cast<u64>(static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), k))); };
+  r.mask = word(2 * N) | (word(2 * N + 1) << 32);
+  r.key = word(2 * N + 2) | (word(2 * N + 3) << 32);
+  return r;
+}
+
 // Index of the brick at offset s e_j + r e_l from b through the link table (kNone if unknown).
 template <typename Real>
 __device__ __forceinline__ uint32_t diag_of(const Dev<Real>& d, uint32_t b, int j, int s, int l, int r) {
@@ -902,90 +942,185 @@ __global__ __launch_bounds__(kWG) void k_grow_fix(Dev<Real> d) {
 }
 
 // ---------------------------------------------------------------------------
-// Flux pass A: transverse fluctuations and corrected states Q_l
+// Flux passes
 // ---------------------------------------------------------------------------
-// Both flux passes load in three phases so the memory round trips overlap:
-// (1) every axis-neighbour brick index, (2) every neighbour row, issued
-// unconditionally (a missing neighbour reads the brick's own row and is zeroed
-// afterwards, so no branch splits the loads), (3) the arithmetic.
+// Pass A computes the corrected states Q_l of every cell and stores them; pass
+// B recomputes its own cells' Q_l (it holds every input already) and reads
+// from neighbour bricks only the face layer of Q_l that its faces need.  Q_l
+// rows are stored with the coordinate field of dimension l moved to the top
+// lane bits, so that a face layer (a_l fixed) is one contiguous block of
+// 64 / side values and a neighbour read touches only those cache lines.
+//
+// Both passes fetch the next brick's links while computing the current one,
+// then load in two phases so the memory round trips overlap: every neighbour
+// row first, issued unconditionally (a missing neighbour reads the permanently
+// empty brick at index cap_b), then the arithmetic.
+
+// Position of lane `lane`'s cell in a stored Q_l row.
+template <int N, int L>
+__device__ __forceinline__ int qpos(int lane) {
+  constexpr int off = brick_off(N, L), bits = brick_bits(N, L);
+  const int low = lane & ((1 << off) - 1);
+  const int a = (lane >> off) & ((1 << bits) - 1);
+  const int high = lane >> (off + bits);
+  return low | (high << off) | (a << (6 - bits));
+}
+// Lane of the cell with the same coordinates as `lane` except a_J = v.
+template <int N, int J>
+__device__ __forceinline__ int lane_with(int lane, int v) {
+  constexpr int off = brick_off(N, J), field = (brick_side(N, J) - 1) << off;
+  return (lane & ~field) | (v << off);
+}
+
+// Value at distance Dd = +-1 along J when the cells of the neighbour brick
+// that a boundary lane needs were loaded at that lane ("face" holds, for a
+// lane with a_J at the boundary, the neighbour cell itself): boundary lanes
+// take the loaded value, the others a shuffle of this brick's own values.
+template <int N, int J, int Dd, typename T>
+__device__ __forceinline__ T nbface(T own_shuffled, T face) {
+  return lane_in(Dir<N, J, Dd>::out) ? face : own_shuffled;
+}
+template <int N, int J, int Dd, typename T>
+__device__ __forceinline__ T own_shift(T own, int lane) {
+  constexpr int side = brick_side(N, J), stride = brick_stride(N, J);
+  if constexpr (side == 2)
+    return xor_shfl<stride>(own);
+  else
+    return __shfl(own, rot_lane<N>(lane, J, Dd));
+}
+
+// Load through the constant address space: for a wave-uniform address this is
+// a scalar load.  Only for data that no kernel writes while the reading kernel
+// runs (brick masks during the flux passes).
+template <typename T>
+__device__ __forceinline__ T load_const(const T* p) {
+  return *(const __attribute__((address_space(4))) T*)(p);
+}
+
+// A wave-uniform value computed by vector instructions, moved to scalar
+// registers (keeps per-kernel constants out of the vector register file).
+__device__ __forceinline__ double to_sgpr(double v) {
+  const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+  const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float to_sgpr(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+// A copy of v that the compiler cannot see through (no instruction emitted).
+template <typename T>
+__device__ __forceinline__ T opaque(T v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
+// Transverse fluctuation T_j of one cell (see the gather form above).
+template <typename Real>
+__device__ __forceinline__ Real t_term(Real p0, Real pm, Real pp, bool ep, Real ub, Real uf) {
+  return rpos(ub) * (p0 - pm) + (ep ? rneg(uf) * (pp - p0) : Real(0));
+}
+// Q_l = P - sum_{j != l} c_j T_j, accumulated term by term so that Q_l is
+// exactly P when every transverse T_j vanishes (with the threshold at zero,
+// an exact zero decides whether a cell grows).
+template <int N, typename Real>
+__device__ __forceinline__ void q_from_t(Real p0, const Real* c, const Real* T, Real* q) {
+#pragma unroll
+  for (int l = 0; l < N; ++l) {
+    Real v = p0;
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+      if (j != l) v = v - c[j] * T[j];
+    q[l] = v;
+  }
+}
+
+// Flux pass A: transverse fluctuations and corrected states Q_l.
 template <int N, int MODEL, typename Real>
 __global__ __launch_bounds__(kWG, kFluxWavesPerEU) void k_flux_a(Dev<Real> d) {
   const Scalars* sb = d.sb;
-  if (!sb->run) return;
-  const uint32_t nb = nb_of(d);
-  const Real* P = cur_p(d);
-  const double dt = sb->dt;
+  // The scalar block is written only between passes: read it as constant.
+  if (!load_const(&sb->run)) return;
+  const uint32_t nb = min(load_const(&sb->nb), d.cap_b);
+  const Real* P = load_const(&sb->cur) ? d.P1 : d.P0;
+  const double dt = load_const(&sb->dt);
   Real c[N];
 #pragma unroll
-  for (int j = 0; j < N; ++j) c[j] = static_cast<Real>(dt / (2.0 * d.h[j]));
+  for (int j = 0; j < N; ++j) c[j] = to_sgpr(static_cast<Real>(dt / (2.0 * d.h[j])));
   const int lane = lane_id();
   double xoff[N];  // this lane's offset from its brick's corner cell centre
 #pragma unroll
   for (int j = 0; j < N; ++j) xoff[j] = static_cast<double>((lane >> brick_off(N, j)) & (brick_side(N, j) - 1)) * d.h[j];
   const WaveRange rg = wave_range(nb);
+  uint32_t meta = meta_fetch<N>(d, rg.begin < rg.end ? rg.begin : kNone, lane);
   for (uint32_t b = rg.begin; b < rg.end; b += rg.step) {
-    uint32_t bm[N], bp[N];
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-      bm[j] = nbr_of(d, b, j, -1);
-      bp[j] = nbr_of(d, b, j, 1);
-    }
-    const u64 m = d.mask[b];
-    const u64 key = d.key[b];
+    const BrickMeta<N> bm = meta_unpack<N>(meta);
     const Real p0 = P[static_cast<size_t>(b) * kLanes + lane];
-    // Missing neighbours read the permanently empty brick at index cap_b.
-    Real Pm[N], Pp[N];
+    // Only the face layer of each neighbour is needed: every lane loads the
+    // neighbour cell of the boundary lane with its other coordinates.
+    Real Fm[N], Fp[N];
     u64 mp[N];
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-      const uint32_t im = bm[j] != kNone ? bm[j] : d.cap_b, ip = bp[j] != kNone ? bp[j] : d.cap_b;
-      Pm[j] = P[static_cast<size_t>(im) * kLanes + lane];
-      Pp[j] = P[static_cast<size_t>(ip) * kLanes + lane];
-      mp[j] = d.mask[ip];
-    }
+    static_for<N>([&](auto Jc) {
+      constexpr int j = decltype(Jc)::value;
+      const uint32_t im = bm.bm[j] != kNone ? bm.bm[j] : d.cap_b, ip = bm.bp[j] != kNone ? bm.bp[j] : d.cap_b;
+      const Real* rm = P + static_cast<size_t>(im) * kLanes;
+      const Real* rp = P + static_cast<size_t>(ip) * kLanes;
+      Fm[j] = rm[lane_with<N, j>(lane, brick_side(N, j) - 1)];
+      Fp[j] = rp[lane_with<N, j>(lane, 0)];
+      mp[j] = load_const(d.mask + ip);
+    });
+    const uint32_t bn = b + rg.step;
+    meta = meta_fetch<N>(d, bn < rg.end ? bn : kNone, lane);
     int64_t B[N];
-    unpack_key<N>(key, B);
+    unpack_key<N>(bm.key, B);
     double xc[N];
 #pragma unroll
     for (int j = 0; j < N; ++j) xc[j] = (d.mean[j] + static_cast<double>(B[j] * brick_side(N, j)) * d.h[j]) + xoff[j];
-    const bool act = (m >> lane) & 1ull;
+    const bool act = lane_in(bm.mask);
     Real T[N];
     static_for<N>([&](auto Jc) {
       constexpr int j = decltype(Jc)::value;
-      const Real pm = nbval<N, j, -1>(p0, Pm[j], lane);
-      const Real pp = nbval<N, j, 1>(p0, Pp[j], lane);
-      const bool ep = nbpresent<N, j, 1>(m, mp[j], lane);
+      Real pm, pp;
+      if constexpr (brick_side(N, j) == 2) {
+        const Real sh = own_shift<N, j, 1>(p0, lane);
+        pm = nbface<N, j, -1>(sh, Fm[j]);
+        pp = nbface<N, j, 1>(sh, Fp[j]);
+      } else {
+        pm = nbface<N, j, -1>(own_shift<N, j, -1>(p0, lane), Fm[j]);
+        pp = nbface<N, j, 1>(own_shift<N, j, 1>(p0, lane), Fp[j]);
+      }
+      const bool ep = lane_in(present_lanes<N, j, 1>(bm.mask, mp[j]));
       double ubd, ufd;
       flux_vels<MODEL, N>(d, xc, j, &ubd, &ufd);
-      const Real ub = static_cast<Real>(ubd), uf = static_cast<Real>(ufd);
-      T[j] = rpos(ub) * (p0 - pm) + (ep ? rneg(uf) * (pp - p0) : Real(0));
+      T[j] = t_term(p0, pm, pp, ep, static_cast<Real>(ubd), static_cast<Real>(ufd));
     });
-    Real* Qb = d.Q + static_cast<size_t>(b) * N * kLanes + lane;
-#pragma unroll
-    for (int l = 0; l < N; ++l) {
-      Real q = p0;
-#pragma unroll
-      for (int j = 0; j < N; ++j)
-        if (j != l) q = q - c[j] * T[j];
-      Qb[l * kLanes] = act ? q : Real(0);
-    }
+    Real q[N];
+    q_from_t<N>(p0, c, T, q);
+    Real* Qb = d.Q + static_cast<size_t>(b) * N * kLanes;
+    static_for<N>([&](auto Lc) {
+      constexpr int l = decltype(Lc)::value;
+      Qb[l * kLanes + qpos<N, l>(lane)] = act ? q[l] : Real(0);
+    });
   }
 }
 
-// ---------------------------------------------------------------------------
-// Flux pass B: face fluxes, high-resolution term, conservative update
-// ---------------------------------------------------------------------------
+// Flux pass B: face fluxes, high-resolution term, conservative update.
 template <int N, int MODEL, typename Real>
-__global__ __launch_bounds__(kWG, sizeof(Real) == 8 ? kFluxWavesPerEU - 1 : kFluxWavesPerEU) void k_flux_b(Dev<Real> d) {
+__global__ __launch_bounds__(kWG, sizeof(Real) == 8 ? kFluxBWavesPerEU64 : kFluxBWavesPerEU32) void k_flux_b(Dev<Real> d) {
   const Scalars* sb = d.sb;
-  if (!sb->run) return;
-  const uint32_t nb = nb_of(d);
-  const Real* P = cur_p(d);
-  Real* Pn = next_p(d);
-  const double dt = sb->dt;
-  Real dth[N];
+  // The scalar block is written only between passes: read it as constant.
+  if (!load_const(&sb->run)) return;
+  const uint32_t nb = min(load_const(&sb->nb), d.cap_b);
+  const uint32_t cur = load_const(&sb->cur);
+  const Real* P = cur ? d.P1 : d.P0;
+  Real* Pn = cur ? d.P0 : d.P1;
+  const double dt = load_const(&sb->dt);
+  Real dth[N], c[N];
 #pragma unroll
-  for (int j = 0; j < N; ++j) dth[j] = static_cast<Real>(dt / d.h[j]);
+  for (int j = 0; j < N; ++j) {
+    dth[j] = static_cast<Real>(dt / d.h[j]);
+    c[j] = static_cast<Real>(dt / (2.0 * d.h[j]));
+  }
   const bool hr = d.limiter != 0;
   const int lane = lane_id();
   double xoff[N];  // this lane's offset from its brick's corner cell centre
@@ -993,59 +1128,79 @@ __global__ __launch_bounds__(kWG, sizeof(Real) == 8 ? kFluxWavesPerEU - 1 : kFlu
   for (int j = 0; j < N; ++j) xoff[j] = static_cast<double>((lane >> brick_off(N, j)) & (brick_side(N, j) - 1)) * d.h[j];
   double vmax = 0.0, vsum = 0.0, vcnt = 0.0;
   const WaveRange rg = wave_range(nb);
+  uint32_t meta = meta_fetch<N>(d, rg.begin < rg.end ? rg.begin : kNone, lane);
   for (uint32_t b = rg.begin; b < rg.end; b += rg.step) {
-    uint32_t bm[N], bp[N];
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-      bm[j] = nbr_of(d, b, j, -1);
-      bp[j] = nbr_of(d, b, j, 1);
-    }
-    const u64 m = d.mask[b];
-    const u64 key = d.key[b];
+    const BrickMeta<N> bm = meta_unpack<N>(meta);
     const size_t o = static_cast<size_t>(b) * kLanes + lane;
     const Real p0 = P[o];
-    const Real* Qb = d.Q + static_cast<size_t>(b) * N * kLanes;
-    Real Pm[N], Pp[N], Qm[N], Qp[N], q[N];
+    Real Pm[N], Pp[N], Qm[N], Qp[N];
     u64 mm[N], mp[N];
-    // Missing neighbours read the permanently empty brick at index cap_b: its
-    // densities and mask are zero; its Q row is never used (no face to it).
-#pragma unroll
-    for (int l = 0; l < N; ++l) {
-      const uint32_t im = bm[l] != kNone ? bm[l] : d.cap_b, ip = bp[l] != kNone ? bp[l] : d.cap_b;
-      Pm[l] = P[static_cast<size_t>(im) * kLanes + lane];
-      Pp[l] = P[static_cast<size_t>(ip) * kLanes + lane];
-      Qm[l] = d.Q[(static_cast<size_t>(im) * N + l) * kLanes + lane];
-      Qp[l] = d.Q[(static_cast<size_t>(ip) * N + l) * kLanes + lane];
-      q[l] = Qb[l * kLanes + lane];
-      mm[l] = d.mask[im];
-      mp[l] = d.mask[ip];
-    }
+    // Full neighbour density rows (the high-resolution term reads distance 2);
+    // Q_l only in the face layer.  The empty brick's Q rows are never used
+    // (its faces have no cell on the far side).
+    static_for<N>([&](auto Lc) {
+      constexpr int l = decltype(Lc)::value;
+      constexpr int side = brick_side(N, l);
+      const uint32_t im = bm.bm[l] != kNone ? bm.bm[l] : d.cap_b, ip = bm.bp[l] != kNone ? bm.bp[l] : d.cap_b;
+      const Real* rm = P + static_cast<size_t>(im) * kLanes;
+      const Real* rp = P + static_cast<size_t>(ip) * kLanes;
+      const Real* qm_row = d.Q + (static_cast<size_t>(im) * N + l) * kLanes;
+      const Real* qp_row = d.Q + (static_cast<size_t>(ip) * N + l) * kLanes;
+      Pm[l] = rm[lane];
+      Pp[l] = rp[lane];
+      Qm[l] = qm_row[qpos<N, l>(lane_with<N, l>(lane, side - 1))];
+      Qp[l] = qp_row[qpos<N, l>(lane_with<N, l>(lane, 0))];
+      mm[l] = load_const(d.mask + im);
+      mp[l] = load_const(d.mask + ip);
+    });
+    const uint32_t bn = b + rg.step;
+    meta = meta_fetch<N>(d, bn < rg.end ? bn : kNone, lane);
     int64_t B[N];
-    unpack_key<N>(key, B);
+    unpack_key<N>(bm.key, B);
     double xc[N];
 #pragma unroll
     for (int j = 0; j < N; ++j) xc[j] = (d.mean[j] + static_cast<double>(B[j] * brick_side(N, j)) * d.h[j]) + xoff[j];
-    const bool act = (m >> lane) & 1ull;
+    const bool act = lane_in(bm.mask);
+    // This brick's own corrected states, as pass A computed them.
+    Real ub[N], uf[N], T[N];
+    static_for<N>([&](auto Lc) {
+      constexpr int l = decltype(Lc)::value;
+      double ubd, ufd;
+      flux_vels<MODEL, N>(d, xc, l, &ubd, &ufd);
+      ub[l] = static_cast<Real>(ubd);
+      uf[l] = static_cast<Real>(ufd);
+      T[l] = t_term(p0, nbval<N, l, -1>(p0, Pm[l], lane), nbval<N, l, 1>(p0, Pp[l], lane),
+                    lane_in(present_lanes<N, l, 1>(bm.mask, mp[l])), ub[l], uf[l]);
+    });
+    Real q[N];
+    q_from_t<N>(p0, c, T, q);
+    // The distance-1 neighbour values are shuffled again below rather than
+    // kept live across both loops (register pressure); the opaque copy of P
+    // stops the compiler from merging the two computations.
+    const Real p0r = opaque(p0);
     Real acc = p0;
     static_for<N>([&](auto Lc) {
       constexpr int l = decltype(Lc)::value;
-      const Real vPm = Pm[l], vPp = Pp[l];
-      const bool em = nbpresent<N, l, -1>(m, mm[l], lane);
-      const bool ep = nbpresent<N, l, 1>(m, mp[l], lane);
-      const Real pm1 = nbval<N, l, -1>(p0, vPm, lane);
-      const Real pp1 = nbval<N, l, 1>(p0, vPp, lane);
-      const Real qm = nbval<N, l, -1>(q[l], Qm[l], lane);
-      const Real qp = nbval<N, l, 1>(q[l], Qp[l], lane);
-      double ubd, ufd;
-      flux_vels<MODEL, N>(d, xc, l, &ubd, &ufd);
-      const Real ub = static_cast<Real>(ubd), uf = static_cast<Real>(ufd);
-      Real fb = rpos(ub) * qm + rneg(ub) * q[l];
-      Real ff = rpos(uf) * q[l] + rneg(uf) * qp;
+      const bool em = lane_in(present_lanes<N, l, -1>(bm.mask, mm[l]));
+      const bool ep = lane_in(present_lanes<N, l, 1>(bm.mask, mp[l]));
+      const Real pm1 = nbval<N, l, -1>(p0r, Pm[l], lane);
+      const Real pp1 = nbval<N, l, 1>(p0r, Pp[l], lane);
+      Real qm, qp;
+      if constexpr (brick_side(N, l) == 2) {
+        const Real sh = own_shift<N, l, 1>(q[l], lane);
+        qm = nbface<N, l, -1>(sh, Qm[l]);
+        qp = nbface<N, l, 1>(sh, Qp[l]);
+      } else {
+        qm = nbface<N, l, -1>(own_shift<N, l, -1>(q[l], lane), Qm[l]);
+        qp = nbface<N, l, 1>(own_shift<N, l, 1>(q[l], lane), Qp[l]);
+      }
+      Real fb = rpos(ub[l]) * qm + rneg(ub[l]) * q[l];
+      Real ff = rpos(uf[l]) * q[l] + rneg(uf[l]) * qp;
       if (hr) {
-        const Real pm2 = nbval<N, l, -2>(p0, vPm, lane);
-        const Real pp2 = nbval<N, l, 2>(p0, vPp, lane);
-        fb += hr_term(ub, dth[l], p0 - pm1, ub > Real(0) ? pm1 - pm2 : pp1 - p0);
-        ff += hr_term(uf, dth[l], pp1 - p0, uf > Real(0) ? p0 - pm1 : pp2 - pp1);
+        const Real pm2 = nbval<N, l, -2>(p0r, Pm[l], lane);
+        const Real pp2 = nbval<N, l, 2>(p0r, Pp[l], lane);
+        fb += hr_term(ub[l], dth[l], p0r - pm1, ub[l] > Real(0) ? pm1 - pm2 : pp1 - p0r);
+        ff += hr_term(uf[l], dth[l], pp1 - p0r, uf[l] > Real(0) ? p0r - pm1 : pp2 - pp1);
       }
       if (em) acc = acc + dth[l] * fb;
       if (ep) acc = acc - dth[l] * ff;
