@@ -350,25 +350,6 @@ __device__ __forceinline__ double face_vel_fwd(const Dev<Real>& d, const double*
   return drift_at<MODEL, N>(xc, j, face_coord(d.mean[j], ii[j] + 1, d.h[j]), d.params);
 }
 
-// Flux-pass velocities at the backward and forward j-faces of a cell with centre xc.
-// Each model's f_j is affine in x_j, so the forward value is the backward one plus
-// (df_j/dx_j) h_j.  Equal to face_vel / face_vel_fwd up to rounding, and used only
-// inside the flux sums, which are continuous in u; the grow and prune decisions and
-// the CFL speed use the exact forms.
-template <int MODEL, int N, typename Real>
-__device__ __forceinline__ void flux_vels(const Dev<Real>& d, const double* xc, int j, double* ub, double* uf) {
-  const double* p = d.params;
-  *ub = drift_at<MODEL, N>(xc, j, xc[j] - 0.5 * d.h[j], p);
-  double dfdx;
-  if constexpr (MODEL == kModelL63)
-    dfdx = j == 0 ? -p[0] : (j == 1 ? -1.0 : -p[2]);
-  else if constexpr (MODEL == kModelL96)
-    dfdx = -1.0;
-  else
-    dfdx = p[j * N + j];
-  *uf = *ub + dfdx * d.h[j];
-}
-
 // S_i = sum_j |f_{i - 1/2 e_j, j}| / h_j (Eq. 8).
 template <int MODEL, int N, typename Real>
 __device__ __forceinline__ double cell_speed(const Dev<Real>& d, const double* xc, const int32_t* ii) {

@@ -1048,9 +1048,6 @@ __global__ __launch_bounds__(kWG, kFluxWavesPerEU) void k_flux_a(Dev<Real> d) {
 #pragma unroll
   for (int j = 0; j < N; ++j) c[j] = to_sgpr(static_cast<Real>(dt / (2.0 * d.h[j])));
   const int lane = lane_id();
-  double xoff[N];  // this lane's offset from its brick's corner cell centre
-#pragma unroll
-  for (int j = 0; j < N; ++j) xoff[j] = static_cast<double>((lane >> brick_off(N, j)) & (brick_side(N, j) - 1)) * d.h[j];
   const WaveRange rg = wave_range(nb);
   uint32_t meta = meta_fetch<N>(d, rg.begin < rg.end ? rg.begin : kNone, lane);
   for (uint32_t b = rg.begin; b < rg.end; b += rg.step) {
@@ -1073,11 +1070,11 @@ __global__ __launch_bounds__(kWG, kFluxWavesPerEU) void k_flux_a(Dev<Real> d) {
     meta = meta_fetch<N>(d, bn < rg.end ? bn : kNone, lane);
     int64_t B[N];
     unpack_key<N>(bm.key, B);
+    int32_t ii[N];
     double xc[N];
-#pragma unroll
-    for (int j = 0; j < N; ++j) xc[j] = (d.mean[j] + static_cast<double>(B[j] * brick_side(N, j)) * d.h[j]) + xoff[j];
-    const bool act = lane_in(bm.mask);
+    cell_of<N>(d, B, lane, ii, xc);
     Real T[N];
+    u64 keep[N];  // lanes whose Q_l is stored for the neighbour bricks
     static_for<N>([&](auto Jc) {
       constexpr int j = decltype(Jc)::value;
       Real pm, pp;
@@ -1090,16 +1087,22 @@ __global__ __launch_bounds__(kWG, kFluxWavesPerEU) void k_flux_a(Dev<Real> d) {
         pp = nbface<N, j, 1>(own_shift<N, j, 1>(p0, lane), Fp[j]);
       }
       const bool ep = lane_in(present_lanes<N, j, 1>(bm.mask, mp[j]));
-      double ubd, ufd;
-      flux_vels<MODEL, N>(d, xc, j, &ubd, &ufd);
-      T[j] = t_term(p0, pm, pp, ep, static_cast<Real>(ubd), static_cast<Real>(ufd));
+      const Real ub = static_cast<Real>(face_vel<MODEL, N>(d, xc, ii, j));
+      const Real uf = static_cast<Real>(face_vel_fwd<MODEL, N>(d, xc, ii, j));
+      T[j] = t_term(p0, pm, pp, ep, ub, uf);
+      // A face layer's Q_l is read across the brick face only by the
+      // downwind neighbour: the +e_j brick when the forward face velocity is
+      // positive, the -e_j brick when the backward one is negative.
+      // Stored per whole face layer (full cache lines, no partial writes).
+      const u64 want = ballot((lane_in(Dir<N, j, 1>::out) && uf > Real(0)) || (lane_in(Dir<N, j, -1>::out) && ub < Real(0))) & bm.mask;
+      keep[j] = ((want & Dir<N, j, 1>::out) ? Dir<N, j, 1>::out : 0ull) | ((want & Dir<N, j, -1>::out) ? Dir<N, j, -1>::out : 0ull);
     });
     Real q[N];
     q_from_t<N>(p0, c, T, q);
     Real* Qb = d.Q + static_cast<size_t>(b) * N * kLanes;
     static_for<N>([&](auto Lc) {
       constexpr int l = decltype(Lc)::value;
-      Qb[l * kLanes + qpos<N, l>(lane)] = act ? q[l] : Real(0);
+      if (lane_in(keep[l])) Qb[l * kLanes + qpos<N, l>(lane)] = lane_in(bm.mask) ? q[l] : Real(0);
     });
   }
 }
@@ -1123,9 +1126,6 @@ __global__ __launch_bounds__(kWG, sizeof(Real) == 8 ? kFluxBWavesPerEU64 : kFlux
   }
   const bool hr = d.limiter != 0;
   const int lane = lane_id();
-  double xoff[N];  // this lane's offset from its brick's corner cell centre
-#pragma unroll
-  for (int j = 0; j < N; ++j) xoff[j] = static_cast<double>((lane >> brick_off(N, j)) & (brick_side(N, j) - 1)) * d.h[j];
   double vmax = 0.0, vsum = 0.0, vcnt = 0.0;
   const WaveRange rg = wave_range(nb);
   uint32_t meta = meta_fetch<N>(d, rg.begin < rg.end ? rg.begin : kNone, lane);
@@ -1133,19 +1133,33 @@ __global__ __launch_bounds__(kWG, sizeof(Real) == 8 ? kFluxBWavesPerEU64 : kFlux
     const BrickMeta<N> bm = meta_unpack<N>(meta);
     const size_t o = static_cast<size_t>(b) * kLanes + lane;
     const Real p0 = P[o];
+    int64_t B[N];
+    unpack_key<N>(bm.key, B);
+    int32_t ii[N];
+    double xc[N];
+    cell_of<N>(d, B, lane, ii, xc);
+    Real ub[N], uf[N];
+    static_for<N>([&](auto Lc) {
+      constexpr int l = decltype(Lc)::value;
+      ub[l] = static_cast<Real>(face_vel<MODEL, N>(d, xc, ii, l));
+      uf[l] = static_cast<Real>(face_vel_fwd<MODEL, N>(d, xc, ii, l));
+    });
     Real Pm[N], Pp[N], Qm[N], Qp[N];
     u64 mm[N], mp[N];
-    // Full neighbour density rows (the high-resolution term reads distance 2);
-    // Q_l only in the face layer.  The empty brick's Q rows are never used
-    // (its faces have no cell on the far side).
+    // Full neighbour density rows (the high-resolution term reads distance 2).
+    // Q_l only in the face layer and only where the face velocity points out
+    // of the neighbour; other lanes read the empty brick's row (always
+    // cached) and never use the value.
     static_for<N>([&](auto Lc) {
       constexpr int l = decltype(Lc)::value;
       constexpr int side = brick_side(N, l);
       const uint32_t im = bm.bm[l] != kNone ? bm.bm[l] : d.cap_b, ip = bm.bp[l] != kNone ? bm.bp[l] : d.cap_b;
       const Real* rm = P + static_cast<size_t>(im) * kLanes;
       const Real* rp = P + static_cast<size_t>(ip) * kLanes;
-      const Real* qm_row = d.Q + (static_cast<size_t>(im) * N + l) * kLanes;
-      const Real* qp_row = d.Q + (static_cast<size_t>(ip) * N + l) * kLanes;
+      const bool need_m = lane_in(Dir<N, l, -1>::out) && ub[l] > Real(0);
+      const bool need_p = lane_in(Dir<N, l, 1>::out) && uf[l] < Real(0);
+      const Real* qm_row = d.Q + (static_cast<size_t>(need_m ? im : d.cap_b) * N + l) * kLanes;
+      const Real* qp_row = d.Q + (static_cast<size_t>(need_p ? ip : d.cap_b) * N + l) * kLanes;
       Pm[l] = rm[lane];
       Pp[l] = rp[lane];
       Qm[l] = qm_row[qpos<N, l>(lane_with<N, l>(lane, side - 1))];
@@ -1155,20 +1169,11 @@ __global__ __launch_bounds__(kWG, sizeof(Real) == 8 ? kFluxBWavesPerEU64 : kFlux
     });
     const uint32_t bn = b + rg.step;
     meta = meta_fetch<N>(d, bn < rg.end ? bn : kNone, lane);
-    int64_t B[N];
-    unpack_key<N>(bm.key, B);
-    double xc[N];
-#pragma unroll
-    for (int j = 0; j < N; ++j) xc[j] = (d.mean[j] + static_cast<double>(B[j] * brick_side(N, j)) * d.h[j]) + xoff[j];
     const bool act = lane_in(bm.mask);
     // This brick's own corrected states, as pass A computed them.
-    Real ub[N], uf[N], T[N];
+    Real T[N];
     static_for<N>([&](auto Lc) {
       constexpr int l = decltype(Lc)::value;
-      double ubd, ufd;
-      flux_vels<MODEL, N>(d, xc, l, &ubd, &ufd);
-      ub[l] = static_cast<Real>(ubd);
-      uf[l] = static_cast<Real>(ufd);
       T[l] = t_term(p0, nbval<N, l, -1>(p0, Pm[l], lane), nbval<N, l, 1>(p0, Pp[l], lane),
                     lane_in(present_lanes<N, l, 1>(bm.mask, mp[l])), ub[l], uf[l]);
     });
@@ -1194,8 +1199,11 @@ __global__ __launch_bounds__(kWG, sizeof(Real) == 8 ? kFluxBWavesPerEU64 : kFlux
         qm = nbface<N, l, -1>(own_shift<N, l, -1>(q[l], lane), Qm[l]);
         qp = nbface<N, l, 1>(own_shift<N, l, 1>(q[l], lane), Qp[l]);
       }
-      Real fb = rpos(ub[l]) * qm + rneg(ub[l]) * q[l];
-      Real ff = rpos(uf[l]) * q[l] + rneg(uf[l]) * qp;
+      // Upwind states: a neighbour's stored Q_l is read only where the face
+      // velocity strictly points out of it (pass A stores no other face
+      // values, and a zero velocity must not meet an unwritten one).
+      Real fb = ub[l] * (ub[l] > Real(0) ? qm : q[l]);
+      Real ff = uf[l] * (uf[l] < Real(0) ? qp : q[l]);
       if (hr) {
         const Real pm2 = nbval<N, l, -2>(p0r, Pm[l], lane);
         const Real pp2 = nbval<N, l, 2>(p0r, Pp[l], lane);
