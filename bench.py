@@ -24,14 +24,25 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 
 def flux_b_bytes_per_brick(n, real_size):
     """Algorithmic bytes of one brick (64 cell slots) in the flux-B pass: density
-    read, n corrected states read, updated density written, brick key, mask and
-    2n axis-neighbour indices.  Neighbour values count zero (perfect reuse)."""
-    return 64 * real_size + 64 * n * real_size + 64 * real_size + 8 + 8 + 4 * 2 * n
+    row read, updated density row written, brick key, mask and 2n axis links,
+    and the upwind face layers of the neighbours' corrected states (one layer of
+    64/2 values per dimension: across each brick face only the downwind brick
+    reads the upwind side's layer).  Neighbour density rows count zero (each is
+    some brick's own row, read once with perfect reuse)."""
+    return 64 * real_size + 64 * real_size + 8 + 8 + 4 * 2 * n + n * 32 * real_size
 
 
 def flux_a_bytes_per_brick(n, real_size):
-    """Flux-A pass: density read, n corrected states written, key, mask, links."""
-    return 64 * real_size + 64 * n * real_size + 8 + 8 + 4 * 2 * n
+    """Flux-A pass: density row read, key, mask and links, and the face layers
+    of Q written for the downwind neighbours (one layer of 64/2 values per
+    dimension on average)."""
+    return 64 * real_size + 8 + 8 + 4 * 2 * n + n * 32 * real_size
+
+
+def fused_bytes_per_brick(n, real_size):
+    """Lower bound for any one-pass form of the whole flux + update: density
+    row in, updated row out, key, mask and links."""
+    return 2 * 64 * real_size + 8 + 8 + 4 * 2 * n
 
 
 def pmc_record(workload):
@@ -195,6 +206,11 @@ def main():
         "phases_ms_per_job": {k: v[0] / args.steps for k, v in prof_sum.items()},
         "flux_passes_cell_updates_per_s": cells_per_step / (avg_a + avg_b),
         "flux_a_gbps": bytes_a / avg_a / 1e9,
+        "flux_step_vs_fused_bound": {
+            "bytes_per_brick": fused_bytes_per_brick(n, real_size),
+            "gbps": fused_bytes_per_brick(n, real_size) * bricks_per_launch / (avg_a + avg_b) / 1e9,
+            "frac": fused_bytes_per_brick(n, real_size) * bricks_per_launch / (avg_a + avg_b) / 1e9 / HBM_PEAK_GBPS,
+        },
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_budget)
