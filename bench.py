@@ -67,6 +67,50 @@ def measured_traffic(rec, bricks_per_launch):
     return per_brick * bricks_per_launch
 
 
+# Capacity (cell slots) per workload: the L96 grids grow about 16-fold over t in [0, 1].
+MAX_CELLS = {"l96_6d": 64 * 8_000_000, "l96_6d_fp32": 64 * 30_000_000}
+
+
+def grid_errors(a, b, cell_volume):
+    """L1 = V * sum |Pa - Pb| and max |Pa - Pb| / max Pb over the union of the two
+    grids (a missing cell counts as P = 0); a and b are (idx, P) exports."""
+    import numpy as np
+    da = dict(zip(map(tuple, a[0]), a[1]))
+    db = dict(zip(map(tuple, b[0]), b[1]))
+    keys = set(da) | set(db)
+    diff = np.fromiter((da.get(k, 0.0) - db.get(k, 0.0) for k in keys), dtype=np.float64, count=len(keys))
+    return {"l1": float(cell_volume * np.abs(diff).sum()), "max_rel": float(np.abs(diff).max() / np.abs(b[1]).max()),
+            "cells": [len(a[0]), len(b[0])]}
+
+
+def fp32_accuracy(G, S):
+    """Error of the FP32 form on the downsampled L96 grid (h = 0.5, thr 1e-5):
+    against the FP64 oracle over the first 0.05 time units (8 steps, what the
+    oracle finishes in under a minute), and against the FP64 GPU path over the
+    whole horizon with the correction."""
+    import oracle
+    import numpy as np
+    base = S.l96_6d_downsampled()
+    c32 = S.with_(base, precision=1)
+    V = float(np.prod(base["h"][:base["n"]]))
+    out = {"workload": "l96_6d_downsampled: Lorenz-96 n=6, h=0.5, thr=1e-5"}
+    g = G.Grid.gaussian(c32, 64 * 200_000)
+    g.step(0.05)
+    gi, gp, _ = g.export()
+    g.close()
+    o = oracle.Oracle(base).init_gaussian()
+    o.step(0.05)
+    oi, op = o.export()[:2]
+    out["vs_fp64_oracle_t0.05"] = grid_errors((gi, gp), (oi, op), V)
+    ex = []
+    for c in (c32, base):
+        g = G.run_scenario(c, max_cells=64 * 2_000_000)
+        ex.append(g.export()[:2])
+        g.close()
+    out["vs_fp64_gpu_full_horizon"] = grid_errors(ex[0], ex[1], V)
+    return out
+
+
 def run_job(G, cfg, max_cells, profile):
     grid = G.Grid.gaussian(cfg, max_cells)
     if profile:
@@ -102,7 +146,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="l96_6d")
-    ap.add_argument("--max-cells", type=int, default=64 * 8_000_000)
+    ap.add_argument("--max-cells", type=int, default=0, help="capacity in cell slots (default: per workload)")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the FP32-form error report")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -123,6 +168,8 @@ def main():
     cfg = S.workload(args.workload)
     n = cfg["n"]
     real_size = 4 if cfg.get("precision", 0) == 1 else 8
+    if not args.max_cells:
+        args.max_cells = MAX_CELLS.get(args.workload, 64 * 8_000_000)
 
     if args.calibrate_copy:  # a plain copy of known size, to scale the HBM byte counters by
         src = torch.ones(args.calibrate_copy, dtype=torch.uint8, device="cuda")
@@ -193,7 +240,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_flux_b",
+            "kernel": f"k_flux_b<{n},{'float' if real_size == 4 else 'double'}>",
             "achieved": achieved,
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
@@ -212,6 +259,8 @@ def main():
             "frac": fused_bytes_per_brick(n, real_size) * bricks_per_launch / (avg_a + avg_b) / 1e9 / HBM_PEAK_GBPS,
         },
     }
+    if real_size == 4 and not args.no_accuracy:
+        line["accuracy"] = fp32_accuracy(G, S)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_budget)
     print(json.dumps(line), flush=True)
