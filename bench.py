@@ -111,6 +111,55 @@ def fp32_accuracy(G, S):
     return out
 
 
+def serving_bench(args):
+    """The serving stream through the device pool: one-at-a-time FP64 pass
+    (for the mean service time and the baseline), then all requests at once
+    (capacity), then Poisson arrivals at offered load rho = lambda E[S]."""
+    import numpy as np
+    import torch
+
+    from paper_2508_13986_amd import scenarios as S
+    from paper_2508_13986_amd import serving as V
+
+    torch.cuda.set_device(0)
+    reqs, gaps = S.serving_requests(args.requests, seed=5)
+    V.one_at_a_time(reqs[:1])  # warm-up: module load and first-touch of the kernels
+    alone = V.one_at_a_time(reqs)
+    s_alone = np.array([a["seconds"] for a in alone])
+    cu = float(sum(a["cell_updates"] for a in alone))
+    pool_bytes = int(args.pool_gib * (1 << 30))
+    burst, mk_b = V.serve(reqs, np.zeros(len(reqs)), pool_bytes, args.max_active)
+    sb = V.summarize(burst, mk_b)
+    lam = args.load / s_alone.mean()
+    pois, mk_p = V.serve(reqs, gaps / lam, pool_bytes, args.max_active)
+    sp = V.summarize(pois, mk_p)
+    n3 = sum(1 for r in reqs if r["n"] == 3)
+    line = {
+        "metric": "serving: aggregate cell-updates/s, mixed Lorenz-63/96 request stream",
+        "value": sb["cell_updates_per_s"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": mk_b * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded request stream: priors, horizons, truth-trajectory measurements)",
+        "config": {"workload": f"serving stream, seed 5: {len(reqs)} requests ({n3} Lorenz-63, {len(reqs) - n3} "
+                               f"Lorenz-96 6D), horizons 0.5-2, 0-4 corrections each",
+                   "max_active": args.max_active, "pool_gib": args.pool_gib, "parallelism": "single GPU"},
+        "one_at_a_time": {"seconds": float(s_alone.sum()), "cell_updates_per_s": cu / float(s_alone.sum()),
+                          "mean_service_s": float(s_alone.mean()), "p50_service_s": float(np.percentile(s_alone, 50)),
+                          "p99_service_s": float(np.percentile(s_alone, 99))},
+        "burst": sb,
+        "poisson": dict(sp, offered_load=args.load, rate_per_s=lam),
+        "speedup_vs_one_at_a_time": sb["cell_updates_per_s"] / (cu / float(s_alone.sum())),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def run_job(G, cfg, max_cells, profile):
     grid = G.Grid.gaussian(cfg, max_cells)
     if profile:
@@ -148,6 +197,10 @@ def main():
     ap.add_argument("--workload", default="l96_6d")
     ap.add_argument("--max-cells", type=int, default=0, help="capacity in cell slots (default: per workload)")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the FP32-form error report")
+    ap.add_argument("--requests", type=int, default=256, help="serving: requests in the stream")
+    ap.add_argument("--load", type=float, default=2.0, help="serving: offered load rho = lambda * E[service]")
+    ap.add_argument("--max-active", type=int, default=16, help="serving: requests running at once")
+    ap.add_argument("--pool-gib", type=float, default=160.0, help="serving: arena of the pool")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -158,6 +211,10 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see the design notes on sharding)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "serving":
+        serving_bench(args)
+        return
 
     import torch
 

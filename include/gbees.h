@@ -149,6 +149,74 @@ int gbees_destroy(gbees_ctx* ctx);
 
 const char* gbees_strerror(int code);
 
+/* ------------------------------------------------------------------------
+ * Serving pool: propagation requests for many objects (each a Gaussian prior,
+ * a horizon and scalar measurements: the problem of Sec. 2 and 5.1 posed per
+ * object) share one caller-owned device arena.  A request is admitted when a
+ * slot is free and a slice of the arena of gbees_arena_bytes(cfg) bytes can be
+ * carved out (so cfg->max_cells sets its footprint); admitted requests run
+ * concurrently, each on its own stream, and leave the pool as soon as they
+ * finish, which frees their slice for the next ones.  The pool allocates no
+ * device memory; it owns one HIP stream, one event and one pinned scalar copy
+ * per slot.  Times are seconds on the pool's monotonic clock.
+ * ---------------------------------------------------------------------- */
+typedef struct gbees_pool gbees_pool;
+
+typedef struct {
+  double t;          /* measurement time in [0, t_end] (later ones are ignored) */
+  int32_t component; /* measured coordinate, 0-based */
+  double y;          /* measured value */
+  double sigma;      /* noise standard deviation > 0 (Eq. 4 with a Gaussian likelihood) */
+} gbees_meas;
+
+typedef struct {
+  int32_t status;      /* 0 waiting, 1 running, 2 done, < 0 the GBEES_E_* code it failed with */
+  double t_submit;     /* when gbees_pool_submit accepted it */
+  double t_admit;      /* when it got its slot and arena slice */
+  double t_done;       /* when its last batch finished on the device (or it failed) */
+  int64_t arena_bytes; /* its footprint */
+  int64_t cells;       /* cells in the result */
+  gbees_stats stats;   /* statistics of the finished propagation */
+} gbees_req_info;
+
+/* arena: device buffer of arena_bytes owned by the caller for the pool's
+ * life; max_active (1..256): requests running at once. */
+int gbees_pool_create(void* arena, size_t arena_bytes, int32_t max_active, gbees_pool** out);
+
+/* Queue a request: initialise from the Gaussian of cfg (as gbees_init_gaussian),
+ * step to each measurement time in order, correct (as gbees_correct), step to
+ * t_end.  Requires cfg->thresh_rel > 0.  meas is copied.  *req receives its id.
+ * GBEES_E_CAPACITY if its footprint exceeds the whole arena.  A request whose
+ * grid outgrows cfg->max_cells ends with status GBEES_E_CAPACITY. */
+int gbees_pool_submit(gbees_pool* pool, const gbees_config* cfg, double t_end, const gbees_meas* meas,
+                      int32_t n_meas, int64_t* req);
+
+/* Advance the pool without waiting on the device: collect finished batches,
+ * enqueue the next batch or correction of every running request, mark the
+ * finished ones done (their slot is freed), admit waiting requests in arrival
+ * order (looking up to three places past one that does not fit).  Either
+ * count may be NULL. */
+int gbees_pool_progress(gbees_pool* pool, int32_t* n_running, int32_t* n_waiting);
+
+int gbees_pool_info(gbees_pool* pool, int64_t req, gbees_req_info* out);
+
+/* The finished request's grid, as gbees_export: idx[count][n], P[count] sorted
+ * by index.  A finished request keeps its grid (and arena slice) on the device
+ * until the first call of this function copies it to the host and frees the
+ * slice.  GBEES_E_STATE while it runs; its error code if it failed;
+ * GBEES_E_BUFFER (with *count set) if capacity < count. */
+int gbees_pool_result(gbees_pool* pool, int64_t req, int64_t capacity, int32_t* idx, double* P, int64_t* count);
+
+/* Forget a finished or failed request, freeing its arena slice if it still
+ * holds one.  Release every finished request: its slice is not reused before. */
+int gbees_pool_release(gbees_pool* pool, int64_t req);
+
+/* Seconds on the pool's clock (0 for a NULL pool). */
+double gbees_pool_clock(gbees_pool* pool);
+
+/* Wait for the pool's streams and release everything but the arena. */
+int gbees_pool_destroy(gbees_pool* pool);
+
 #ifdef __cplusplus
 }
 #endif

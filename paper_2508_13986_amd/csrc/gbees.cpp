@@ -5,7 +5,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <deque>
 #include <cstring>
 #include <new>
 #include <unordered_map>
@@ -211,10 +213,41 @@ struct gbees_ctx {
       return fail(GBEES_E_DEVICE);
     if (hipStreamSynchronize(stream) != hipSuccess) return fail(GBEES_E_DEVICE);
     prof.harvest();
+    return absorb();
+  }
+  // Host bookkeeping after a fresh copy of the scalar block landed in hsb.
+  int absorb() {
     nb_est = std::max<uint32_t>(std::min<uint32_t>(hsb.nb, L.cap_b), 64);
     host_steps = static_cast<int64_t>(hsb.steps);
     if (hsb.status != 0) return fail(hsb.status == gbees::kErrRange ? GBEES_E_RANGE : GBEES_E_CAPACITY);
     return GBEES_OK;
+  }
+  // Enqueue up to K steps toward t_stop (steps past it are no-ops on the
+  // device), with a prune or renormalisation after every prune_every-th step.
+  void enqueue_steps(double t_stop, int K) {
+    const bool prune_on = cfg.prune_every > 0;
+    const bool thr_on = cfg.thresh_rel > 0.0;
+    kt->set_tstop(dev, stream, t_stop);
+    const uint32_t g = G();
+    for (int k = 0; k < K; ++k) {
+      kt->step(dev, stream, g, &prof);
+      ++host_steps;
+      if (prune_on && host_steps % cfg.prune_every == 0) {
+        if (thr_on)
+          kt->prune(dev, stream, g, true, &prof);
+        else
+          kt->normalise(dev, stream, g, gbees::kGateStep);
+      }
+    }
+  }
+  // Steps for the next batch: enough to reach t_stop at the last step size.
+  void adapt_batch(double t_stop) {
+    if (hsb.dt_last > 0.0) {
+      const double est = std::ceil((t_stop - hsb.t) / hsb.dt_last);
+      batch = static_cast<int>(std::min(std::max(est + 1.0, 1.0), 256.0));
+    } else {
+      batch = std::min(batch * 2, 256);
+    }
   }
   int fail(int code) {
     if (status == GBEES_OK) status = code;
@@ -346,17 +379,8 @@ u64 key_of_cell_n(int n, const int32_t* idx, bool* ok) {
   }
 }
 
-}  // namespace
-
-extern "C" {
-
-size_t gbees_arena_bytes(const gbees_config* cfg) {
-  Layout L;
-  if (!cfg || !make_layout(*cfg, &L)) return 0;
-  return L.total;
-}
-
-int gbees_init_gaussian(const gbees_config* cfg, void* arena, size_t arena_bytes, void* hip_stream, gbees_ctx** out) {
+// Validate, lay out the arena and enqueue the Gaussian initialisation (no wait).
+int init_gaussian_begin(const gbees_config* cfg, void* arena, size_t arena_bytes, void* hip_stream, gbees_ctx** out) {
   if (!out) return GBEES_E_ARG;
   *out = nullptr;
   if (!cfg || !(cfg->thresh_rel > 0.0 && cfg->thresh_rel < 1.0)) return GBEES_E_ARG;
@@ -401,7 +425,26 @@ int gbees_init_gaussian(const gbees_config* cfg, void* arena, size_t arena_bytes
   gb = std::min<uint64_t>(std::max<uint64_t>((gb + 7) / 8 * 8, 8), gbees::kMaxWG);
   c->nb_est = static_cast<uint32_t>(std::min<uint64_t>(box_count, c->L.cap_b));
   c->kt->init_gaussian(c->dev, c->stream, c->G(), static_cast<uint32_t>(gb));
-  const int rc = c->sync_read();
+  *out = c;
+  return GBEES_OK;
+}
+
+
+}  // namespace
+
+extern "C" {
+
+size_t gbees_arena_bytes(const gbees_config* cfg) {
+  Layout L;
+  if (!cfg || !make_layout(*cfg, &L)) return 0;
+  return L.total;
+}
+
+int gbees_init_gaussian(const gbees_config* cfg, void* arena, size_t arena_bytes, void* hip_stream, gbees_ctx** out) {
+  gbees_ctx* c = nullptr;
+  int rc = init_gaussian_begin(cfg, arena, arena_bytes, hip_stream, &c);
+  if (rc != GBEES_OK) return rc;
+  rc = c->sync_read();
   if (rc != GBEES_OK) {
     delete c;
     return rc;
@@ -493,37 +536,19 @@ int gbees_step(gbees_ctx* c, double t_stop, int64_t max_steps, gbees_stats* out)
   int rc = check_ctx(c);
   if (rc != GBEES_OK) return rc;
   if (!std::isfinite(t_stop) || t_stop < c->hsb.t) return GBEES_E_ARG;
-  const bool prune_on = c->cfg.prune_every > 0;
-  const bool thr_on = c->cfg.thresh_rel > 0.0;
   if (c->hsb.t < t_stop) {
-    c->kt->set_tstop(c->dev, c->stream, t_stop);
     int64_t taken = 0;
     while (true) {
       int K = c->batch;
       if (max_steps > 0) K = static_cast<int>(std::min<int64_t>(K, max_steps - taken));
       const int64_t before = c->host_steps;
-      const uint32_t G = c->G();
-      for (int k = 0; k < K; ++k) {
-        c->kt->step(c->dev, c->stream, G, &c->prof);
-        ++c->host_steps;
-        if (prune_on && c->host_steps % c->cfg.prune_every == 0) {
-          if (thr_on)
-            c->kt->prune(c->dev, c->stream, G, true, &c->prof);
-          else
-            c->kt->normalise(c->dev, c->stream, G, gbees::kGateStep);
-        }
-      }
+      c->enqueue_steps(t_stop, K);
       rc = c->sync_read();
       if (rc != GBEES_OK) return rc;
       taken += c->host_steps - before;
       if (c->hsb.t >= t_stop) break;
       if (max_steps > 0 && taken >= max_steps) break;
-      if (c->hsb.dt_last > 0.0) {
-        const double est = std::ceil((t_stop - c->hsb.t) / c->hsb.dt_last);
-        c->batch = static_cast<int>(std::min(std::max(est + 1.0, 1.0), 256.0));
-      } else {
-        c->batch = std::min(c->batch * 2, 256);
-      }
+      c->adapt_batch(t_stop);
     }
   }
   return gbees_get_stats(c, out);
@@ -696,6 +721,360 @@ const char* gbees_strerror(int code) {
     case GBEES_E_STATE: return "context is in an error state";
     default: return "unknown error";
   }
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Serving pool: many propagation requests share one caller-owned arena.
+// Each admitted request gets a slice of the arena sized by its footprint
+// (gbees_arena_bytes of its configuration), its own stream and a slot with a
+// pinned copy of its scalar block.  gbees_pool_progress never waits on the
+// device: it harvests finished batches (event queries), enqueues the next
+// batch of steps or the next correction of each request, exports finished
+// requests, frees their slices and admits waiting requests in arrival order
+// as slots and memory become free.  Batches of different requests therefore
+// run concurrently on the device.
+// ---------------------------------------------------------------------------
+namespace {
+
+using PoolClock = std::chrono::steady_clock;
+
+// First-fit allocator over [0, bytes) of the pool arena (host bookkeeping only).
+class SliceAllocator {
+ public:
+  explicit SliceAllocator(size_t bytes) { free_.push_back({0, bytes}); }
+  bool take(size_t bytes, size_t* off) {
+    bytes = align_up(bytes);
+    for (size_t k = 0; k < free_.size(); ++k) {
+      if (free_[k].size >= bytes) {
+        *off = free_[k].off;
+        free_[k].off += bytes;
+        free_[k].size -= bytes;
+        if (free_[k].size == 0) free_.erase(free_.begin() + static_cast<std::ptrdiff_t>(k));
+        return true;
+      }
+    }
+    return false;
+  }
+  void give(size_t off, size_t bytes) {
+    bytes = align_up(bytes);
+    auto it = std::lower_bound(free_.begin(), free_.end(), off, [](const Span& s, size_t o) { return s.off < o; });
+    it = free_.insert(it, Span{off, bytes});
+    if (it + 1 != free_.end() && it->off + it->size == (it + 1)->off) {
+      it->size += (it + 1)->size;
+      free_.erase(it + 1);
+    }
+    if (it != free_.begin() && (it - 1)->off + (it - 1)->size == it->off) {
+      (it - 1)->size += it->size;
+      free_.erase(it);
+    }
+  }
+
+ private:
+  struct Span {
+    size_t off, size;
+  };
+  std::vector<Span> free_;
+};
+
+struct PoolRequest {
+  gbees_config cfg{};
+  double t_end = 0.0;
+  std::vector<gbees_meas> meas;  // sorted by time, within [0, t_end]
+  size_t next_meas = 0;
+  size_t bytes = 0, off = 0;
+  int32_t status = 0;  // 0 pending, 1 running, 2 done, < 0 error code
+  int slot = -1;
+  gbees_ctx* ctx = nullptr;
+  double t_submit = 0.0, t_admit = 0.0, t_done = 0.0;
+  gbees_stats stats{};
+  std::vector<CellRow> rows;
+};
+
+struct PoolSlot {
+  hipStream_t stream = nullptr;
+  hipEvent_t event = nullptr;
+  Scalars* hsb = nullptr;  // pinned
+  int64_t req = -1;
+  bool inflight = false;
+};
+
+}  // namespace
+
+struct gbees_pool {
+  char* base = nullptr;
+  size_t total = 0;
+  SliceAllocator slices{0};
+  std::vector<PoolSlot> slots;
+  Scalars* pinned = nullptr;
+  std::deque<int64_t> pending;
+  std::unordered_map<int64_t, PoolRequest> reqs;
+  int64_t next_id = 1;
+  PoolClock::time_point t0 = PoolClock::now();
+
+  double now() const { return std::chrono::duration<double>(PoolClock::now() - t0).count(); }
+
+  // Enqueue the copy of the scalar block and the completion event of slot s.
+  int mark(int s) {
+    PoolSlot& sl = slots[s];
+    gbees_ctx* c = reqs[sl.req].ctx;
+    if (hipMemcpyAsync(sl.hsb, c->base + c->L.sb, sizeof(Scalars), hipMemcpyDeviceToHost, sl.stream) != hipSuccess ||
+        hipEventRecord(sl.event, sl.stream) != hipSuccess)
+      return GBEES_E_DEVICE;
+    sl.inflight = true;
+    return GBEES_OK;
+  }
+
+  // The request leaves its slot.  A failed request also gives back its arena
+  // slice; a finished one keeps it (its grid stays on the device) until the
+  // caller releases it.
+  void retire(PoolRequest& r, int32_t status) {
+    if (status != 2) {
+      if (r.ctx) {
+        gbees_destroy(r.ctx);
+        r.ctx = nullptr;
+      }
+      slices.give(r.off, r.bytes);
+    }
+    slots[r.slot].req = -1;
+    slots[r.slot].inflight = false;
+    r.slot = -1;
+    r.status = status;
+    r.t_done = now();
+  }
+
+  // The request's scalar block has landed: take its next action.
+  int advance(int64_t id) {
+    PoolRequest& r = reqs[id];
+    gbees_ctx* c = r.ctx;
+    const bool has_meas = r.next_meas < r.meas.size();
+    const double target = has_meas ? r.meas[r.next_meas].t : r.t_end;
+    if (c->hsb.t < target) {
+      c->adapt_batch(target);
+      c->enqueue_steps(target, c->batch);
+      return mark(r.slot);
+    }
+    if (has_meas) {
+      const gbees_meas& m = r.meas[r.next_meas++];
+      const bool prune = c->cfg.prune_every > 0 && c->cfg.thresh_rel > 0.0;
+      c->kt->correct(c->dev, c->stream, c->G(), m.component, m.y, m.sigma, prune);
+      return mark(r.slot);
+    }
+    // Finished: the scalar block just read is the final one.
+    double vol = 1.0;
+    for (int j = 0; j < c->cfg.n; ++j) vol = vol * c->cfg.h[j];
+    gbees_stats& st = r.stats;
+    st.t = c->hsb.t;
+    st.dt_last = c->hsb.dt_last;
+    st.mass = vol * c->hsb.sum;
+    st.max_p = c->hsb.maxp;
+    std::memcpy(&st.smax, &c->hsb.smax_bits, sizeof(double));
+    st.steps = static_cast<int64_t>(c->hsb.steps);
+    st.cell_updates = static_cast<int64_t>(c->hsb.cell_updates);
+    st.brick_updates = static_cast<int64_t>(c->hsb.brick_updates);
+    st.cells = static_cast<int64_t>(c->hsb.cells);
+    st.bricks = static_cast<int64_t>(std::min<uint32_t>(c->hsb.nb, c->L.cap_b));
+    st.prunes = static_cast<int64_t>(c->hsb.prunes);
+    st.grow_bricks = static_cast<int64_t>(c->hsb.grow_bricks);
+    st.inserted = static_cast<int64_t>(c->hsb.inserted);
+    retire(r, 2);
+    return GBEES_OK;
+  }
+
+  int admit() {
+    for (auto it = pending.begin(); it != pending.end();) {
+      int s = -1;
+      for (size_t k = 0; k < slots.size(); ++k)
+        if (slots[k].req < 0) {
+          s = static_cast<int>(k);
+          break;
+        }
+      if (s < 0) return GBEES_OK;
+      PoolRequest& r = reqs[*it];
+      size_t off = 0;
+      if (!slices.take(r.bytes, &off)) {
+        // Requests behind a large one may still fit: look a few places further.
+        if (it - pending.begin() >= 3) return GBEES_OK;
+        ++it;
+        continue;
+      }
+      r.off = off;
+      gbees_ctx* c = nullptr;
+      const int rc = init_gaussian_begin(&r.cfg, base + off, r.bytes, slots[s].stream, &c);
+      r.t_admit = now();
+      if (rc != GBEES_OK) {
+        slices.give(off, r.bytes);
+        r.status = rc;
+        r.t_done = r.t_admit;
+        it = pending.erase(it);
+        continue;
+      }
+      r.ctx = c;
+      r.slot = s;
+      r.status = 1;
+      slots[s].req = *it;
+      it = pending.erase(it);
+      const int m = mark(s);
+      if (m != GBEES_OK) return m;
+    }
+    return GBEES_OK;
+  }
+};
+
+extern "C" {
+
+int gbees_pool_create(void* arena, size_t arena_bytes, int32_t max_active, gbees_pool** out) {
+  if (!out || !arena || arena_bytes < kAlign || max_active < 1 || max_active > 256) return GBEES_E_ARG;
+  *out = nullptr;
+  auto* p = new (std::nothrow) gbees_pool();
+  if (!p) return GBEES_E_ARG;
+  p->base = static_cast<char*>(arena);
+  p->total = arena_bytes / kAlign * kAlign;
+  p->slices = SliceAllocator(p->total);
+  if (hipHostMalloc(reinterpret_cast<void**>(&p->pinned), sizeof(Scalars) * max_active, hipHostMallocDefault) !=
+      hipSuccess) {
+    delete p;
+    return GBEES_E_DEVICE;
+  }
+  p->slots.resize(max_active);
+  for (int s = 0; s < max_active; ++s) {
+    p->slots[s].hsb = p->pinned + s;
+    if (hipStreamCreateWithFlags(&p->slots[s].stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&p->slots[s].event, hipEventDisableTiming) != hipSuccess) {
+      gbees_pool_destroy(p);
+      return GBEES_E_DEVICE;
+    }
+  }
+  *out = p;
+  return GBEES_OK;
+}
+
+int gbees_pool_submit(gbees_pool* p, const gbees_config* cfg, double t_end, const gbees_meas* meas, int32_t nm,
+                      int64_t* req) {
+  if (!p || !cfg || !req || nm < 0 || (nm > 0 && !meas) || !std::isfinite(t_end) || t_end < 0.0) return GBEES_E_ARG;
+  const size_t bytes = gbees_arena_bytes(cfg);
+  if (bytes == 0 || !(cfg->thresh_rel > 0.0)) return GBEES_E_ARG;
+  if (align_up(bytes) > p->total) return GBEES_E_CAPACITY;  // could never be admitted
+  PoolRequest r;
+  r.cfg = *cfg;
+  r.t_end = t_end;
+  for (int32_t k = 0; k < nm; ++k) {
+    const gbees_meas& m = meas[k];
+    if (m.component < 0 || m.component >= cfg->n || !(m.sigma > 0.0) || !std::isfinite(m.y) || !(m.t >= 0.0))
+      return GBEES_E_ARG;
+    if (m.t <= t_end) r.meas.push_back(m);
+  }
+  std::stable_sort(r.meas.begin(), r.meas.end(), [](const gbees_meas& a, const gbees_meas& b) { return a.t < b.t; });
+  r.bytes = bytes;
+  r.t_submit = p->now();
+  const int64_t id = p->next_id++;
+  p->reqs.emplace(id, std::move(r));
+  p->pending.push_back(id);
+  *req = id;
+  return GBEES_OK;
+}
+
+int gbees_pool_progress(gbees_pool* p, int32_t* n_running, int32_t* n_pending) {
+  if (!p) return GBEES_E_ARG;
+  for (size_t s = 0; s < p->slots.size(); ++s) {
+    PoolSlot& sl = p->slots[s];
+    if (sl.req < 0 || !sl.inflight) continue;
+    const hipError_t q = hipEventQuery(sl.event);
+    if (q == hipErrorNotReady) continue;
+    PoolRequest& r = p->reqs[sl.req];
+    sl.inflight = false;
+    if (q != hipSuccess) {
+      p->retire(r, GBEES_E_DEVICE);
+      continue;
+    }
+    r.ctx->hsb = *sl.hsb;
+    const int rc = r.ctx->absorb();
+    if (rc != GBEES_OK) {
+      p->retire(r, rc);
+      continue;
+    }
+    const int a = p->advance(sl.req);
+    if (a != GBEES_OK) p->retire(r, a);
+  }
+  const int rc = p->admit();
+  int32_t running = 0;
+  for (const auto& sl : p->slots) running += sl.req >= 0 ? 1 : 0;
+  if (n_running) *n_running = running;
+  if (n_pending) *n_pending = static_cast<int32_t>(p->pending.size());
+  return rc;
+}
+
+int gbees_pool_info(gbees_pool* p, int64_t req, gbees_req_info* out) {
+  if (!p || !out) return GBEES_E_ARG;
+  auto it = p->reqs.find(req);
+  if (it == p->reqs.end()) return GBEES_E_ARG;
+  const PoolRequest& r = it->second;
+  out->status = r.status;
+  out->t_submit = r.t_submit;
+  out->t_admit = r.t_admit;
+  out->t_done = r.t_done;
+  out->arena_bytes = static_cast<int64_t>(r.bytes);
+  out->cells = r.stats.cells;
+  out->stats = r.stats;
+  return GBEES_OK;
+}
+
+int gbees_pool_result(gbees_pool* p, int64_t req, int64_t capacity, int32_t* idx, double* P, int64_t* count) {
+  if (!p || !count) return GBEES_E_ARG;
+  auto it = p->reqs.find(req);
+  if (it == p->reqs.end()) return GBEES_E_ARG;
+  PoolRequest& r = it->second;
+  if (r.status < 0) return r.status;
+  if (r.status != 2) return GBEES_E_STATE;
+  if (r.ctx) {  // first call: copy the grid out (waits for the request's stream)
+    const int rc = host_cells(r.ctx, &r.rows);
+    if (rc != GBEES_OK) return rc;
+    gbees_destroy(r.ctx);
+    r.ctx = nullptr;
+    p->slices.give(r.off, r.bytes);
+  }
+  *count = static_cast<int64_t>(r.rows.size());
+  if (capacity < *count) return GBEES_E_BUFFER;
+  if (*count > 0 && (!idx || !P)) return GBEES_E_ARG;
+  const int n = r.cfg.n;
+  for (size_t k = 0; k < r.rows.size(); ++k) {
+    for (int j = 0; j < n; ++j) idx[k * n + j] = r.rows[k].idx[j];
+    P[k] = r.rows[k].p;
+  }
+  return GBEES_OK;
+}
+
+int gbees_pool_release(gbees_pool* p, int64_t req) {
+  if (!p) return GBEES_E_ARG;
+  auto it = p->reqs.find(req);
+  if (it == p->reqs.end()) return GBEES_E_ARG;
+  PoolRequest& r = it->second;
+  if (r.status == 0 || r.status == 1) return GBEES_E_STATE;
+  if (r.ctx) {
+    gbees_destroy(r.ctx);
+    r.ctx = nullptr;
+    p->slices.give(r.off, r.bytes);
+  }
+  p->reqs.erase(it);
+  return GBEES_OK;
+}
+
+double gbees_pool_clock(gbees_pool* p) { return p ? p->now() : 0.0; }
+
+int gbees_pool_destroy(gbees_pool* p) {
+  if (!p) return GBEES_E_ARG;
+  for (auto& sl : p->slots)
+    if (sl.stream) hipStreamSynchronize(sl.stream);
+  for (auto& kv : p->reqs)
+    if (kv.second.ctx) gbees_destroy(kv.second.ctx);
+  for (auto& sl : p->slots) {
+    if (sl.event) hipEventDestroy(sl.event);
+    if (sl.stream) hipStreamDestroy(sl.stream);
+  }
+  if (p->pinned) hipHostFree(p->pinned);
+  delete p;
+  return GBEES_OK;
 }
 
 }  // extern "C"

@@ -89,12 +89,39 @@ def lib():
         L.gbees_destroy.argtypes = [vp]
         L.gbees_strerror.restype = ctypes.c_char_p
         L.gbees_strerror.argtypes = [ctypes.c_int]
+        pp = ctypes.POINTER(ctypes.c_int32)
+        L.gbees_pool_create.argtypes = [vp, ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(vp)]
+        L.gbees_pool_submit.argtypes = [vp, cfgp, dbl, ctypes.POINTER(GbeesMeas), ctypes.c_int32, ctypes.POINTER(i64)]
+        L.gbees_pool_progress.argtypes = [vp, pp, pp]
+        L.gbees_pool_info.argtypes = [vp, i64, ctypes.POINTER(GbeesReqInfo)]
+        L.gbees_pool_result.argtypes = [vp, i64, i64, vp, vp, ctypes.POINTER(i64)]
+        L.gbees_pool_release.argtypes = [vp, i64]
+        L.gbees_pool_clock.argtypes = [vp]
+        L.gbees_pool_clock.restype = dbl
+        L.gbees_pool_destroy.argtypes = [vp]
         for name in ("gbees_init_gaussian", "gbees_init_cells", "gbees_step", "gbees_correct", "gbees_marginals",
                      "gbees_export", "gbees_get_stats", "gbees_probe_stats", "gbees_profile",
-                     "gbees_profile_read", "gbees_destroy"):
+                     "gbees_profile_read", "gbees_destroy", "gbees_pool_create", "gbees_pool_submit",
+                     "gbees_pool_progress", "gbees_pool_info", "gbees_pool_result", "gbees_pool_release",
+                     "gbees_pool_destroy"):
             getattr(L, name).restype = ctypes.c_int
         _LIB = L
     return _LIB
+
+class GbeesMeas(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("component", ctypes.c_int32), ("y", ctypes.c_double), ("sigma", ctypes.c_double)]
+
+
+class GbeesReqInfo(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("t_submit", ctypes.c_double),
+        ("t_admit", ctypes.c_double),
+        ("t_done", ctypes.c_double),
+        ("arena_bytes", ctypes.c_int64),
+        ("cells", ctypes.c_int64),
+        ("stats", GbeesStats),
+    ]
 
 
 def _fill(arr, values):
@@ -247,6 +274,78 @@ class Grid:
 
 def _stats_dict(s: GbeesStats) -> dict:
     return {f: getattr(s, f) for f, _ in GbeesStats._fields_}
+
+
+class Pool:
+    """The serving pool (gbees_pool_*): requests share one device arena and run
+    concurrently; ``progress()`` advances them without waiting on the device."""
+
+    def __init__(self, arena_bytes: int, max_active: int = 16, device=None):
+        import torch
+
+        dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=dev)
+        self._h = ctypes.c_void_p()
+        _check(lib().gbees_pool_create(ctypes.c_void_p(self.arena.data_ptr()), ctypes.c_size_t(self.arena.numel()),
+                                       int(max_active), ctypes.byref(self._h)), "gbees_pool_create")
+        self.n = {}
+
+    def submit(self, cfg: dict, max_cells: int, t_end=None, measurements=None) -> int:
+        """Queue the scenario ``cfg`` (its t_end and measurements unless given)."""
+        c = make_config(cfg, max_cells)
+        meas = cfg.get("measurements", []) if measurements is None else measurements
+        arr = (GbeesMeas * max(len(meas), 1))()
+        for k, (t, comp, y, sig) in enumerate(meas):
+            arr[k] = GbeesMeas(float(t), int(comp), float(y), float(sig))
+        rid = ctypes.c_int64(0)
+        te = float(cfg["t_end"] if t_end is None else t_end)
+        _check(lib().gbees_pool_submit(self._h, ctypes.byref(c), te, arr, len(meas), ctypes.byref(rid)),
+               "gbees_pool_submit")
+        self.n[rid.value] = int(cfg["n"])
+        return rid.value
+
+    def progress(self):
+        """(running, waiting) after one non-blocking pass."""
+        r, w = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(lib().gbees_pool_progress(self._h, ctypes.byref(r), ctypes.byref(w)), "gbees_pool_progress")
+        return r.value, w.value
+
+    def info(self, rid: int) -> dict:
+        i = GbeesReqInfo()
+        _check(lib().gbees_pool_info(self._h, int(rid), ctypes.byref(i)), "gbees_pool_info")
+        st = {f: getattr(i.stats, f) for f, _ in GbeesStats._fields_}
+        return {"status": i.status, "t_submit": i.t_submit, "t_admit": i.t_admit, "t_done": i.t_done,
+                "arena_bytes": i.arena_bytes, "cells": i.cells, "stats": st}
+
+    def result(self, rid: int):
+        """(idx int32[count, n], P float64[count]) of a finished request."""
+        cnt = ctypes.c_int64(0)
+        code = lib().gbees_pool_result(self._h, int(rid), 0, None, None, ctypes.byref(cnt))
+        if code not in (OK, E_BUFFER):
+            raise GbeesError(code, "gbees_pool_result")
+        n = self.n[int(rid)]
+        idx = np.zeros((cnt.value, n), dtype=np.int32)
+        P = np.zeros(cnt.value, dtype=np.float64)
+        _check(lib().gbees_pool_result(self._h, int(rid), cnt.value, idx.ctypes.data_as(ctypes.c_void_p),
+                                       P.ctypes.data_as(ctypes.c_void_p), ctypes.byref(cnt)), "gbees_pool_result")
+        return idx, P
+
+    def release(self, rid: int):
+        _check(lib().gbees_pool_release(self._h, int(rid)), "gbees_pool_release")
+
+    def clock(self) -> float:
+        return float(lib().gbees_pool_clock(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().gbees_pool_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def run_scenario(cfg, max_cells=None, grid=None):

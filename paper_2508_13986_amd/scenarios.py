@@ -174,3 +174,70 @@ def uniform_config(n, u, h=1.0, mean=None, thresh_rel=0.0, **kw):
     mean = [0.0] * n if mean is None else mean
     cov = kw.pop("cov", np.eye(n))
     return _base(n, UNIFORM, list(u), h, mean, cov, thresh_rel, 1.0, **kw)
+
+
+# ---------------------------------------------------------------------------
+# Serving stream: many independent objects of uneven grid size.  Each request
+# picks Lorenz '63 or Lorenz '96 (n = 6) with equal odds, a cell width, a mean
+# within +-2 of the workload mean, a covariance scale in [0.25, 2], a horizon
+# in [0.5, 2] and 0..4 scalar measurements of random components at sorted
+# uniform times, drawn from its own seeded truth trajectory (RK4, step 1e-3).
+# Thresholds 1e-5 (L63) and 1e-2 (L96) give initial grids of ~1e3 to ~2e6
+# cells.  Arrival gaps are unit-rate exponentials; a driver divides them by
+# the arrival rate it wants.
+# ---------------------------------------------------------------------------
+
+def _serving_truth(cfg, times, comps, sigma, seed, dt=1e-3):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = cfg["n"]
+    L = np.linalg.cholesky(np.asarray(cfg["cov"], dtype=np.float64))
+    x = np.asarray(cfg["mean"], dtype=np.float64) + L @ rng.standard_normal(n)
+    out, t = [], 0.0
+    for tk, c in zip(times, comps):
+        steps = int(round((tk - t) / dt))
+        for _ in range(steps):
+            k1 = _truth_drift(cfg, x)
+            k2 = _truth_drift(cfg, x + 0.5 * dt * k1)
+            k3 = _truth_drift(cfg, x + 0.5 * dt * k2)
+            k4 = _truth_drift(cfg, x + dt * k3)
+            x = x + (dt / 6.0) * (k1 + 2 * k2 + 2 * k3 + k4)
+        t = steps * dt + t
+        out.append((float(tk), int(c), float(x[c] + sigma * rng.standard_normal()), float(sigma)))
+    return out
+
+
+def initial_cells_estimate(cfg):
+    """Lattice points of the initial ellipsoid, by its volume in cell units."""
+    from math import gamma, pi
+    n = cfg["n"]
+    cov = np.asarray(cfg["cov"], dtype=np.float64)
+    r2 = 2.0 * np.log(1.0 / cfg["thresh_rel"])
+    vol = pi ** (n / 2) / gamma(n / 2 + 1) * r2 ** (n / 2) * np.sqrt(np.linalg.det(cov)) / np.prod(cfg["h"][:n])
+    return float(vol)
+
+
+def serving_requests(n_req=256, seed=5):
+    """(requests, unit-rate arrival offsets) of the serving stream."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    reqs = []
+    for k in range(n_req):
+        if rng.random() < 0.5:
+            n, model, params = 3, L63, lorenz63()
+            h = [0.5, 0.25][int(rng.integers(2))]
+            mean = np.array([-11.5, -10.0, 9.5]) + rng.uniform(-2.0, 2.0, 3)
+            cov, thr, sigma = rng.uniform(0.25, 2.0) * np.eye(3), 1e-5, 1.0
+        else:
+            n, model, params = 6, L96, lorenz96(4.0)
+            h = [0.3, 0.25][int(rng.integers(2))]
+            mean = np.array([4.5, 4.0, 4.0, 4.0, 4.0, 4.0]) + rng.uniform(-2.0, 2.0, 6)
+            cov, thr, sigma = rng.uniform(0.25, 2.0) * 0.25 * np.eye(6), 1e-2, 0.5
+        T = float(rng.uniform(0.5, 2.0))
+        m = int(rng.integers(0, 5))
+        times = np.sort(rng.uniform(0.0, T, m))
+        comps = rng.integers(0, n, m)
+        d = _base(n, model, params, h, mean, cov, thr, T)
+        d["measurements"] = _serving_truth(d, times, comps, sigma, seed=seed * 100003 + k)
+        d["request"] = k
+        reqs.append(d)
+    gaps = rng.exponential(1.0, n_req)
+    return reqs, np.cumsum(gaps) - gaps[0]

@@ -1,0 +1,125 @@
+"""Serving pool (gbees_pool_*): results in the mix equal results alone, admission
+by arena footprint, and the error paths.  Runs on the GPU through the C ABI."""
+import numpy as np
+import pytest
+
+from paper_2508_13986_amd import scenarios as S
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    from paper_2508_13986_amd import gbees
+
+    gbees.lib()
+    return gbees
+
+
+def small_requests(k):
+    reqs, _ = S.serving_requests(64)
+    out = [r for r in reqs if S.initial_cells_estimate(r) < 4e4]
+    return out[:k]
+
+
+def cap(r):
+    return 64 * (200_000 if r["n"] == 6 else 8_000)
+
+
+def alone(G, r):
+    g = G.run_scenario(r, max_cells=cap(r))
+    res = g.export()[:2]
+    g.close()
+    return res
+
+
+def assert_same(a, b, label):
+    (ai, ap), (bi, bp) = a, b
+    assert len(ai) == len(bi) and np.array_equal(ai, bi), f"{label}: membership differs"
+    assert np.abs(ap - bp).max() <= TOL * np.abs(bp).max(), label
+
+
+def drain(pool, ids, max_seconds=120.0):
+    """Drive the pool until every request ended; fetch each finished grid at
+    once (which frees its arena slice).  Returns {id: (info, result or None)}."""
+    import time
+
+    done = {}
+    t0 = time.monotonic()
+    while len(done) < len(ids):
+        pool.progress()
+        for rid in ids:
+            if rid not in done:
+                inf = pool.info(rid)
+                if inf["status"] == 2:
+                    done[rid] = (inf, pool.result(rid))
+                elif inf["status"] < 0:
+                    done[rid] = (inf, None)
+        assert time.monotonic() - t0 < max_seconds, "pool did not drain"
+    return done
+
+
+def test_pool_results_equal_alone(G):
+    """Six requests of both models in a burst through three slots: each result
+    equals the same request run alone through the plain path."""
+    reqs = small_requests(6)
+    assert {r["n"] for r in reqs} == {3, 6}
+    ref = [alone(G, r) for r in reqs]
+    pool = G.Pool(sum(G.arena_bytes(r, cap(r)) for r in reqs) + (1 << 20), max_active=3)
+    ids = [pool.submit(r, cap(r)) for r in reqs]
+    out = drain(pool, ids)
+    running = sorted((i["t_admit"], i["t_done"]) for i, _ in out.values())
+    for k, (rid, r) in enumerate(zip(ids, reqs)):
+        assert out[rid][0]["status"] == 2
+        assert_same(out[rid][1], ref[k], f"request {k}")
+        pool.release(rid)
+    # never more than three at once
+    for t, _ in running:
+        assert sum(1 for a, b in running if a <= t < b) <= 3
+    pool.close()
+
+
+def test_pool_admits_by_footprint(G):
+    """An arena that holds one request at a time: requests run one after the
+    other even with free slots, and their results are unchanged."""
+    reqs = [r for r in small_requests(12) if r["n"] == 3][:3]
+    sizes = [G.arena_bytes(r, cap(r)) for r in reqs]
+    assert len(reqs) == 3 and len(set(sizes)) == 1
+    pool = G.Pool(sizes[0] + 4096, max_active=4)
+    ids = [pool.submit(r, cap(r)) for r in reqs]
+    out = drain(pool, ids)
+    spans = sorted((out[i][0]["t_admit"], out[i][0]["t_done"]) for i in ids)
+    for (a0, b0), (a1, b1) in zip(spans, spans[1:]):
+        assert a1 >= b0
+    for rid, r in zip(ids, reqs):
+        assert_same(out[rid][1], alone(G, r), "serial")
+        pool.release(rid)
+    pool.close()
+
+
+def test_pool_error_paths(G):
+    reqs = small_requests(2)
+    r = reqs[0]
+    pool = G.Pool(G.arena_bytes(r, cap(r)) + 4096, max_active=2)
+    with pytest.raises(G.GbeesError) as e:
+        pool.submit(r, cap(r) * 64)  # footprint beyond the whole arena
+    assert e.value.code == G.E_CAPACITY
+    bad = pool.submit(r, 64 * 16)  # outgrows 16 bricks
+    out = drain(pool, [bad])
+    assert out[bad][0]["status"] == G.E_CAPACITY
+    with pytest.raises(G.GbeesError) as e:
+        pool.result(bad)
+    assert e.value.code == G.E_CAPACITY
+    pool.release(bad)
+    ok = pool.submit(r, cap(r))  # the slice came back: the pool still serves
+    out = drain(pool, [ok])
+    assert out[ok][0]["status"] == 2
+    assert_same(out[ok][1], alone(G, r), "after failure")
+    pool.close()
