@@ -7,7 +7,10 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <deque>
+#include <mutex>
+#include <thread>
 #include <cstring>
 #include <new>
 #include <unordered_map>
@@ -728,13 +731,13 @@ const char* gbees_strerror(int code) {
 // ---------------------------------------------------------------------------
 // Serving pool: many propagation requests share one caller-owned arena.
 // Each admitted request gets a slice of the arena sized by its footprint
-// (gbees_arena_bytes of its configuration), its own stream and a slot with a
-// pinned copy of its scalar block.  gbees_pool_progress never waits on the
-// device: it harvests finished batches (event queries), enqueues the next
-// batch of steps or the next correction of each request, exports finished
-// requests, frees their slices and admits waiting requests in arrival order
-// as slots and memory become free.  Batches of different requests therefore
-// run concurrently on the device.
+// (gbees_arena_bytes of its configuration) and its own stream, and is run by
+// one of the pool's worker threads: initialise, step to each measurement
+// time, correct, step to the horizon, exactly as the single-grid calls do.
+// Worker threads enqueue in parallel, so requests overlap on the device and a
+// request whose stream queue is full blocks only its own thread.
+// gbees_pool_progress admits waiting requests in arrival order as workers and
+// arena slices become free; it never waits on the device.
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -782,23 +785,33 @@ struct PoolRequest {
   gbees_config cfg{};
   double t_end = 0.0;
   std::vector<gbees_meas> meas;  // sorted by time, within [0, t_end]
-  size_t next_meas = 0;
   size_t bytes = 0, off = 0;
-  int32_t status = 0;  // 0 pending, 1 running, 2 done, < 0 error code
-  int slot = -1;
+  int32_t status = 0;  // 0 waiting, 1 running, 2 done, < 0 error code
+  hipStream_t stream = nullptr;
   gbees_ctx* ctx = nullptr;
   double t_submit = 0.0, t_admit = 0.0, t_done = 0.0;
   gbees_stats stats{};
   std::vector<CellRow> rows;
+  bool exported = false;
 };
 
-struct PoolSlot {
-  hipStream_t stream = nullptr;
-  hipEvent_t event = nullptr;
-  Scalars* hsb = nullptr;  // pinned
-  int64_t req = -1;
-  bool inflight = false;
-};
+// Run one request to the end on its own stream (called by a worker thread,
+// which owns the request while its status is 1).
+int run_request(PoolRequest& r, char* base) {
+  gbees_ctx* c = nullptr;
+  int rc = init_gaussian_begin(&r.cfg, base + r.off, r.bytes, r.stream, &c);
+  if (rc != GBEES_OK) return rc;
+  r.ctx = c;
+  rc = c->sync_read();
+  for (size_t k = 0; rc == GBEES_OK && k <= r.meas.size(); ++k) {
+    const double target = k < r.meas.size() ? r.meas[k].t : r.t_end;
+    if (c->hsb.t < target) rc = gbees_step(c, target, 0, nullptr);
+    if (rc == GBEES_OK && k < r.meas.size())
+      rc = gbees_correct(c, r.meas[k].component, r.meas[k].y, r.meas[k].sigma);
+  }
+  if (rc == GBEES_OK) rc = gbees_get_stats(c, &r.stats);
+  return rc;
+}
 
 }  // namespace
 
@@ -806,120 +819,52 @@ struct gbees_pool {
   char* base = nullptr;
   size_t total = 0;
   SliceAllocator slices{0};
-  std::vector<PoolSlot> slots;
-  Scalars* pinned = nullptr;
-  std::deque<int64_t> pending;
+  std::mutex mu;
+  std::condition_variable work_cv;
+  std::deque<int64_t> pending;  // waiting for a worker and a slice
+  std::deque<int64_t> ready;    // admitted, waiting for a worker to pick up
   std::unordered_map<int64_t, PoolRequest> reqs;
+  std::vector<std::thread> workers;
+  int busy = 0, max_active = 0;
+  bool stop = false;
   int64_t next_id = 1;
   PoolClock::time_point t0 = PoolClock::now();
 
   double now() const { return std::chrono::duration<double>(PoolClock::now() - t0).count(); }
 
-  // Enqueue the copy of the scalar block and the completion event of slot s.
-  int mark(int s) {
-    PoolSlot& sl = slots[s];
-    gbees_ctx* c = reqs[sl.req].ctx;
-    if (hipMemcpyAsync(sl.hsb, c->base + c->L.sb, sizeof(Scalars), hipMemcpyDeviceToHost, sl.stream) != hipSuccess ||
-        hipEventRecord(sl.event, sl.stream) != hipSuccess)
-      return GBEES_E_DEVICE;
-    sl.inflight = true;
-    return GBEES_OK;
+  void worker() {
+    hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu);
+    while (true) {
+      work_cv.wait(lk, [&] { return stop || !ready.empty(); });
+      if (stop && ready.empty()) return;
+      const int64_t id = ready.front();
+      ready.pop_front();
+      PoolRequest& r = reqs[id];
+      lk.unlock();
+      const int rc = run_request(r, base);
+      lk.lock();
+      r.t_done = now();
+      r.status = rc == GBEES_OK ? 2 : rc;
+      if (rc != GBEES_OK) free_request(r);
+      --busy;
+    }
   }
 
-  // The request leaves its slot.  A failed request also gives back its arena
-  // slice; a finished one keeps it (its grid stays on the device) until the
-  // caller releases it.
-  void retire(PoolRequest& r, int32_t status) {
-    if (status != 2) {
-      if (r.ctx) {
-        gbees_destroy(r.ctx);
-        r.ctx = nullptr;
-      }
+  // Give back the device side of a request (caller holds mu or owns r).
+  void free_request(PoolRequest& r) {
+    if (r.ctx) {
+      gbees_destroy(r.ctx);
+      r.ctx = nullptr;
+    }
+    if (r.stream) {
+      hipStreamDestroy(r.stream);
+      r.stream = nullptr;
       slices.give(r.off, r.bytes);
     }
-    slots[r.slot].req = -1;
-    slots[r.slot].inflight = false;
-    r.slot = -1;
-    r.status = status;
-    r.t_done = now();
   }
 
-  // The request's scalar block has landed: take its next action.
-  int advance(int64_t id) {
-    PoolRequest& r = reqs[id];
-    gbees_ctx* c = r.ctx;
-    const bool has_meas = r.next_meas < r.meas.size();
-    const double target = has_meas ? r.meas[r.next_meas].t : r.t_end;
-    if (c->hsb.t < target) {
-      c->adapt_batch(target);
-      c->enqueue_steps(target, c->batch);
-      return mark(r.slot);
-    }
-    if (has_meas) {
-      const gbees_meas& m = r.meas[r.next_meas++];
-      const bool prune = c->cfg.prune_every > 0 && c->cfg.thresh_rel > 0.0;
-      c->kt->correct(c->dev, c->stream, c->G(), m.component, m.y, m.sigma, prune);
-      return mark(r.slot);
-    }
-    // Finished: the scalar block just read is the final one.
-    double vol = 1.0;
-    for (int j = 0; j < c->cfg.n; ++j) vol = vol * c->cfg.h[j];
-    gbees_stats& st = r.stats;
-    st.t = c->hsb.t;
-    st.dt_last = c->hsb.dt_last;
-    st.mass = vol * c->hsb.sum;
-    st.max_p = c->hsb.maxp;
-    std::memcpy(&st.smax, &c->hsb.smax_bits, sizeof(double));
-    st.steps = static_cast<int64_t>(c->hsb.steps);
-    st.cell_updates = static_cast<int64_t>(c->hsb.cell_updates);
-    st.brick_updates = static_cast<int64_t>(c->hsb.brick_updates);
-    st.cells = static_cast<int64_t>(c->hsb.cells);
-    st.bricks = static_cast<int64_t>(std::min<uint32_t>(c->hsb.nb, c->L.cap_b));
-    st.prunes = static_cast<int64_t>(c->hsb.prunes);
-    st.grow_bricks = static_cast<int64_t>(c->hsb.grow_bricks);
-    st.inserted = static_cast<int64_t>(c->hsb.inserted);
-    retire(r, 2);
-    return GBEES_OK;
-  }
-
-  int admit() {
-    for (auto it = pending.begin(); it != pending.end();) {
-      int s = -1;
-      for (size_t k = 0; k < slots.size(); ++k)
-        if (slots[k].req < 0) {
-          s = static_cast<int>(k);
-          break;
-        }
-      if (s < 0) return GBEES_OK;
-      PoolRequest& r = reqs[*it];
-      size_t off = 0;
-      if (!slices.take(r.bytes, &off)) {
-        // Requests behind a large one may still fit: look a few places further.
-        if (it - pending.begin() >= 3) return GBEES_OK;
-        ++it;
-        continue;
-      }
-      r.off = off;
-      gbees_ctx* c = nullptr;
-      const int rc = init_gaussian_begin(&r.cfg, base + off, r.bytes, slots[s].stream, &c);
-      r.t_admit = now();
-      if (rc != GBEES_OK) {
-        slices.give(off, r.bytes);
-        r.status = rc;
-        r.t_done = r.t_admit;
-        it = pending.erase(it);
-        continue;
-      }
-      r.ctx = c;
-      r.slot = s;
-      r.status = 1;
-      slots[s].req = *it;
-      it = pending.erase(it);
-      const int m = mark(s);
-      if (m != GBEES_OK) return m;
-    }
-    return GBEES_OK;
-  }
+  int device = 0;
 };
 
 extern "C" {
@@ -929,23 +874,15 @@ int gbees_pool_create(void* arena, size_t arena_bytes, int32_t max_active, gbees
   *out = nullptr;
   auto* p = new (std::nothrow) gbees_pool();
   if (!p) return GBEES_E_ARG;
-  p->base = static_cast<char*>(arena);
-  p->total = arena_bytes / kAlign * kAlign;
-  p->slices = SliceAllocator(p->total);
-  if (hipHostMalloc(reinterpret_cast<void**>(&p->pinned), sizeof(Scalars) * max_active, hipHostMallocDefault) !=
-      hipSuccess) {
+  if (hipGetDevice(&p->device) != hipSuccess) {
     delete p;
     return GBEES_E_DEVICE;
   }
-  p->slots.resize(max_active);
-  for (int s = 0; s < max_active; ++s) {
-    p->slots[s].hsb = p->pinned + s;
-    if (hipStreamCreateWithFlags(&p->slots[s].stream, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&p->slots[s].event, hipEventDisableTiming) != hipSuccess) {
-      gbees_pool_destroy(p);
-      return GBEES_E_DEVICE;
-    }
-  }
+  p->base = static_cast<char*>(arena);
+  p->total = arena_bytes / kAlign * kAlign;
+  p->slices = SliceAllocator(p->total);
+  p->max_active = max_active;
+  for (int k = 0; k < max_active; ++k) p->workers.emplace_back([p] { p->worker(); });
   *out = p;
   return GBEES_OK;
 }
@@ -967,6 +904,7 @@ int gbees_pool_submit(gbees_pool* p, const gbees_config* cfg, double t_end, cons
   }
   std::stable_sort(r.meas.begin(), r.meas.end(), [](const gbees_meas& a, const gbees_meas& b) { return a.t < b.t; });
   r.bytes = bytes;
+  std::lock_guard<std::mutex> lk(p->mu);
   r.t_submit = p->now();
   const int64_t id = p->next_id++;
   p->reqs.emplace(id, std::move(r));
@@ -975,38 +913,46 @@ int gbees_pool_submit(gbees_pool* p, const gbees_config* cfg, double t_end, cons
   return GBEES_OK;
 }
 
-int gbees_pool_progress(gbees_pool* p, int32_t* n_running, int32_t* n_pending) {
+int gbees_pool_progress(gbees_pool* p, int32_t* n_running, int32_t* n_waiting) {
   if (!p) return GBEES_E_ARG;
-  for (size_t s = 0; s < p->slots.size(); ++s) {
-    PoolSlot& sl = p->slots[s];
-    if (sl.req < 0 || !sl.inflight) continue;
-    const hipError_t q = hipEventQuery(sl.event);
-    if (q == hipErrorNotReady) continue;
-    PoolRequest& r = p->reqs[sl.req];
-    sl.inflight = false;
-    if (q != hipSuccess) {
-      p->retire(r, GBEES_E_DEVICE);
-      continue;
+  int admitted = 0;
+  int rc = GBEES_OK;
+  {
+    std::lock_guard<std::mutex> lk(p->mu);
+    // Admit in arrival order; a request that does not fit may be passed by the
+    // next three.
+    for (auto it = p->pending.begin(); it != p->pending.end() && p->busy < p->max_active;) {
+      PoolRequest& r = p->reqs[*it];
+      size_t off = 0;
+      if (!p->slices.take(r.bytes, &off)) {
+        if (it - p->pending.begin() >= 3) break;
+        ++it;
+        continue;
+      }
+      if (hipStreamCreateWithFlags(&r.stream, hipStreamNonBlocking) != hipSuccess) {
+        p->slices.give(off, r.bytes);
+        r.stream = nullptr;
+        rc = GBEES_E_DEVICE;
+        break;
+      }
+      r.off = off;
+      r.status = 1;
+      r.t_admit = p->now();
+      p->ready.push_back(*it);
+      ++p->busy;
+      ++admitted;
+      it = p->pending.erase(it);
     }
-    r.ctx->hsb = *sl.hsb;
-    const int rc = r.ctx->absorb();
-    if (rc != GBEES_OK) {
-      p->retire(r, rc);
-      continue;
-    }
-    const int a = p->advance(sl.req);
-    if (a != GBEES_OK) p->retire(r, a);
+    if (n_running) *n_running = p->busy;
+    if (n_waiting) *n_waiting = static_cast<int32_t>(p->pending.size());
   }
-  const int rc = p->admit();
-  int32_t running = 0;
-  for (const auto& sl : p->slots) running += sl.req >= 0 ? 1 : 0;
-  if (n_running) *n_running = running;
-  if (n_pending) *n_pending = static_cast<int32_t>(p->pending.size());
+  if (admitted) p->work_cv.notify_all();
   return rc;
 }
 
 int gbees_pool_info(gbees_pool* p, int64_t req, gbees_req_info* out) {
   if (!p || !out) return GBEES_E_ARG;
+  std::lock_guard<std::mutex> lk(p->mu);
   auto it = p->reqs.find(req);
   if (it == p->reqs.end()) return GBEES_E_ARG;
   const PoolRequest& r = it->second;
@@ -1015,24 +961,25 @@ int gbees_pool_info(gbees_pool* p, int64_t req, gbees_req_info* out) {
   out->t_admit = r.t_admit;
   out->t_done = r.t_done;
   out->arena_bytes = static_cast<int64_t>(r.bytes);
-  out->cells = r.stats.cells;
-  out->stats = r.stats;
+  out->cells = r.status == 2 ? r.stats.cells : 0;
+  std::memset(&out->stats, 0, sizeof(out->stats));
+  if (r.status == 2) out->stats = r.stats;
   return GBEES_OK;
 }
 
 int gbees_pool_result(gbees_pool* p, int64_t req, int64_t capacity, int32_t* idx, double* P, int64_t* count) {
   if (!p || !count) return GBEES_E_ARG;
+  std::lock_guard<std::mutex> lk(p->mu);
   auto it = p->reqs.find(req);
   if (it == p->reqs.end()) return GBEES_E_ARG;
   PoolRequest& r = it->second;
   if (r.status < 0) return r.status;
   if (r.status != 2) return GBEES_E_STATE;
-  if (r.ctx) {  // first call: copy the grid out (waits for the request's stream)
+  if (!r.exported) {  // first call: copy the grid out and free the device side
     const int rc = host_cells(r.ctx, &r.rows);
     if (rc != GBEES_OK) return rc;
-    gbees_destroy(r.ctx);
-    r.ctx = nullptr;
-    p->slices.give(r.off, r.bytes);
+    r.exported = true;
+    p->free_request(r);
   }
   *count = static_cast<int64_t>(r.rows.size());
   if (capacity < *count) return GBEES_E_BUFFER;
@@ -1047,15 +994,12 @@ int gbees_pool_result(gbees_pool* p, int64_t req, int64_t capacity, int32_t* idx
 
 int gbees_pool_release(gbees_pool* p, int64_t req) {
   if (!p) return GBEES_E_ARG;
+  std::lock_guard<std::mutex> lk(p->mu);
   auto it = p->reqs.find(req);
   if (it == p->reqs.end()) return GBEES_E_ARG;
   PoolRequest& r = it->second;
   if (r.status == 0 || r.status == 1) return GBEES_E_STATE;
-  if (r.ctx) {
-    gbees_destroy(r.ctx);
-    r.ctx = nullptr;
-    p->slices.give(r.off, r.bytes);
-  }
+  p->free_request(r);
   p->reqs.erase(it);
   return GBEES_OK;
 }
@@ -1064,15 +1008,14 @@ double gbees_pool_clock(gbees_pool* p) { return p ? p->now() : 0.0; }
 
 int gbees_pool_destroy(gbees_pool* p) {
   if (!p) return GBEES_E_ARG;
-  for (auto& sl : p->slots)
-    if (sl.stream) hipStreamSynchronize(sl.stream);
-  for (auto& kv : p->reqs)
-    if (kv.second.ctx) gbees_destroy(kv.second.ctx);
-  for (auto& sl : p->slots) {
-    if (sl.event) hipEventDestroy(sl.event);
-    if (sl.stream) hipStreamDestroy(sl.stream);
+  {
+    std::lock_guard<std::mutex> lk(p->mu);
+    p->stop = true;
+    p->pending.clear();  // never admitted
   }
-  if (p->pinned) hipHostFree(p->pinned);
+  p->work_cv.notify_all();
+  for (auto& t : p->workers) t.join();  // running requests finish first
+  for (auto& kv : p->reqs) p->free_request(kv.second);
   delete p;
   return GBEES_OK;
 }

@@ -19,7 +19,7 @@ from . import scenarios as S
 # Lorenz '96 grids at thr 1e-2 spread along the unstable directions: measured
 # growth from 0.4x to 240x over the horizons of the stream, up to 8.3e6 cells.
 GROWTH = {3: 16.0, 6: 24.0}
-FLOOR = {3: 2.5e5, 6: 4.0e6}
+FLOOR = {3: 2.5e5, 6: 8.0e6}
 
 
 def capacity_for(cfg, factor=1.0):
@@ -56,7 +56,7 @@ def one_at_a_time(reqs, results=False):
     return out
 
 
-def serve(reqs, arrivals, pool_bytes, max_active=16, results=False, spin=0.0):
+def serve(reqs, arrivals, pool_bytes, max_active=16, results=False, spin=2e-4):
     """Submit request k at time arrivals[k] (seconds from start) and drive the
     pool until every request has finished.  A request that outgrows its
     capacity is resubmitted with four times as much, keeping its arrival time."""
