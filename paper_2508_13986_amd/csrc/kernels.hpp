@@ -1008,6 +1008,22 @@ __device__ __forceinline__ float to_sgpr(float v) {
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
+// Raw buffer loads from one brick row: the row's base and size form a scalar
+// buffer descriptor, so per-lane addressing is a 32-bit byte offset, and an
+// offset at or past the size (kOob) returns 0 without touching memory.
+constexpr uint32_t kOob = 0x80000000u;
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void* row, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(row), 0, static_cast<int>(bytes), 0x00020000);
+}
+__device__ __forceinline__ double row_load(__amdgpu_buffer_rsrc_t r, uint32_t off, double) {
+  const u32x2_t v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+  return __hiloint2double(static_cast<int>(v.y), static_cast<int>(v.x));
+}
+__device__ __forceinline__ float row_load(__amdgpu_buffer_rsrc_t r, uint32_t off, float) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
 // A copy of v that the compiler cannot see through (no instruction emitted).
 template <typename T>
 __device__ __forceinline__ T opaque(T v) {
@@ -1059,11 +1075,12 @@ __global__ __launch_bounds__(kWG, kFluxWavesPerEU) void k_flux_a(Dev<Real> d) {
     u64 mp[N];
     static_for<N>([&](auto Jc) {
       constexpr int j = decltype(Jc)::value;
+      constexpr uint32_t kRow = kLanes * sizeof(Real);
       const uint32_t im = bm.bm[j] != kNone ? bm.bm[j] : d.cap_b, ip = bm.bp[j] != kNone ? bm.bp[j] : d.cap_b;
-      const Real* rm = P + static_cast<size_t>(im) * kLanes;
-      const Real* rp = P + static_cast<size_t>(ip) * kLanes;
-      Fm[j] = rm[lane_with<N, j>(lane, brick_side(N, j) - 1)];
-      Fp[j] = rp[lane_with<N, j>(lane, 0)];
+      Fm[j] = row_load(row_rsrc(P + static_cast<size_t>(im) * kLanes, kRow),
+                       lane_with<N, j>(lane, brick_side(N, j) - 1) * sizeof(Real), Real(0));
+      Fp[j] = row_load(row_rsrc(P + static_cast<size_t>(ip) * kLanes, kRow), lane_with<N, j>(lane, 0) * sizeof(Real),
+                       Real(0));
       mp[j] = load_const(d.mask + ip);
     });
     const uint32_t bn = b + rg.step;
@@ -1126,7 +1143,8 @@ __global__ __launch_bounds__(kWG, sizeof(Real) == 8 ? kFluxBWavesPerEU64 : kFlux
   }
   const bool hr = d.limiter != 0;
   const int lane = lane_id();
-  double vmax = 0.0, vsum = 0.0, vcnt = 0.0;
+  double vmax = 0.0, vsum = 0.0;
+  uint32_t ncells = 0;  // wave-uniform
   const WaveRange rg = wave_range(nb);
   uint32_t meta = meta_fetch<N>(d, rg.begin < rg.end ? rg.begin : kNone, lane);
   for (uint32_t b = rg.begin; b < rg.end; b += rg.step) {
@@ -1148,22 +1166,20 @@ __global__ __launch_bounds__(kWG, sizeof(Real) == 8 ? kFluxBWavesPerEU64 : kFlux
     u64 mm[N], mp[N];
     // Full neighbour density rows (the high-resolution term reads distance 2).
     // Q_l only in the face layer and only where the face velocity points out
-    // of the neighbour; other lanes read the empty brick's row (always
-    // cached) and never use the value.
+    // of the neighbour; other lanes load nothing (out-of-range offset).
     static_for<N>([&](auto Lc) {
       constexpr int l = decltype(Lc)::value;
       constexpr int side = brick_side(N, l);
+      constexpr uint32_t kRow = kLanes * sizeof(Real);
       const uint32_t im = bm.bm[l] != kNone ? bm.bm[l] : d.cap_b, ip = bm.bp[l] != kNone ? bm.bp[l] : d.cap_b;
-      const Real* rm = P + static_cast<size_t>(im) * kLanes;
-      const Real* rp = P + static_cast<size_t>(ip) * kLanes;
       const bool need_m = lane_in(Dir<N, l, -1>::out) && ub[l] > Real(0);
       const bool need_p = lane_in(Dir<N, l, 1>::out) && uf[l] < Real(0);
-      const Real* qm_row = d.Q + (static_cast<size_t>(need_m ? im : d.cap_b) * N + l) * kLanes;
-      const Real* qp_row = d.Q + (static_cast<size_t>(need_p ? ip : d.cap_b) * N + l) * kLanes;
-      Pm[l] = rm[lane];
-      Pp[l] = rp[lane];
-      Qm[l] = qm_row[qpos<N, l>(lane_with<N, l>(lane, side - 1))];
-      Qp[l] = qp_row[qpos<N, l>(lane_with<N, l>(lane, 0))];
+      Pm[l] = row_load(row_rsrc(P + static_cast<size_t>(im) * kLanes, kRow), lane * sizeof(Real), Real(0));
+      Pp[l] = row_load(row_rsrc(P + static_cast<size_t>(ip) * kLanes, kRow), lane * sizeof(Real), Real(0));
+      Qm[l] = row_load(row_rsrc(d.Q + (static_cast<size_t>(im) * N + l) * kLanes, kRow),
+                       need_m ? qpos<N, l>(lane_with<N, l>(lane, side - 1)) * sizeof(Real) : kOob, Real(0));
+      Qp[l] = row_load(row_rsrc(d.Q + (static_cast<size_t>(ip) * N + l) * kLanes, kRow),
+                       need_p ? qpos<N, l>(lane_with<N, l>(lane, 0)) * sizeof(Real) : kOob, Real(0));
       mm[l] = load_const(d.mask + im);
       mp[l] = load_const(d.mask + ip);
     });
@@ -1215,14 +1231,13 @@ __global__ __launch_bounds__(kWG, sizeof(Real) == 8 ? kFluxBWavesPerEU64 : kFlux
     });
     const Real out = act ? acc : Real(0);
     Pn[o] = out;
-    if (act) {
-      const double v = static_cast<double>(out);
-      vmax = fmax(vmax, v);
-      vsum += v;
-      vcnt += 1.0;
-    }
+    // Absent cells hold 0: they leave the sum unchanged and cannot raise the
+    // maximum above its start value 0.
+    vmax = fmax(vmax, static_cast<double>(out));
+    vsum += static_cast<double>(out);
+    ncells += static_cast<uint32_t>(__builtin_popcountll(bm.mask));
   }
-  wg_store3(vmax, vsum, vcnt, d.dpart);
+  wg_store3(vmax, vsum, lane == 0 ? static_cast<double>(ncells) : 0.0, d.dpart);
 }
 
 // ---------------------------------------------------------------------------
