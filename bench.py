@@ -160,13 +160,15 @@ def serving_bench(args):
     print(json.dumps(line), flush=True)
 
 
-def run_job(G, cfg, max_cells, profile):
+def run_job(G, cfg, max_cells, profile, probe=False):
     grid = G.Grid.gaussian(cfg, max_cells)
     if profile:
         grid.profile(True)
     G.run_scenario(cfg, grid=grid)
     st = grid.stats()
     prof = grid.profile_read() if profile else None
+    if probe:  # hashtable probe lengths on the final grid (one sub-millisecond kernel)
+        st["probes"] = grid.probe_stats(1 << 20)
     grid.close()
     return st, prof
 
@@ -244,8 +246,8 @@ def main():
     totals = {"cell_updates": 0, "brick_updates": 0, "steps": 0, "grow_bricks": 0, "inserted": 0}
     prof_sum = {}
     last = None
-    for _ in range(args.steps):
-        st, prof = run_job(G, cfg, args.max_cells, profile=True)
+    for k in range(args.steps):
+        st, prof = run_job(G, cfg, args.max_cells, profile=True, probe=(k == args.steps - 1))
         for k in totals:
             totals[k] += st[k]
         for k, (ms, cnt) in prof.items():
@@ -293,6 +295,7 @@ def main():
             "brick_occupancy": cells_per_step / (64 * bricks_per_launch),
             "grow_bricks_per_step": totals["grow_bricks"] / max(totals["steps"], 1),
             "cells_inserted_per_step": totals["inserted"] / max(totals["steps"], 1),
+            "hash_probes_final_grid": last.get("probes"),
             "parallelism": "single GPU",
         },
         "roofline": {

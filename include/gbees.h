@@ -180,7 +180,9 @@ typedef struct {
 } gbees_req_info;
 
 /* arena: device buffer of arena_bytes owned by the caller for the pool's
- * life; max_active (1..256): requests running at once. */
+ * life; max_active (1..256): requests running at once, each on one of the
+ * pool's max_active worker threads.  All pool calls may come from any thread;
+ * gbees_pool_result and gbees_pool_release of one request must not overlap. */
 int gbees_pool_create(void* arena, size_t arena_bytes, int32_t max_active, gbees_pool** out);
 
 /* Queue a request: initialise from the Gaussian of cfg (as gbees_init_gaussian),

@@ -969,15 +969,23 @@ int gbees_pool_info(gbees_pool* p, int64_t req, gbees_req_info* out) {
 
 int gbees_pool_result(gbees_pool* p, int64_t req, int64_t capacity, int32_t* idx, double* P, int64_t* count) {
   if (!p || !count) return GBEES_E_ARG;
-  std::lock_guard<std::mutex> lk(p->mu);
+  std::unique_lock<std::mutex> lk(p->mu);
   auto it = p->reqs.find(req);
   if (it == p->reqs.end()) return GBEES_E_ARG;
   PoolRequest& r = it->second;
   if (r.status < 0) return r.status;
   if (r.status != 2) return GBEES_E_STATE;
-  if (!r.exported) {  // first call: copy the grid out and free the device side
-    const int rc = host_cells(r.ctx, &r.rows);
+  if (!r.exported) {
+    // First call: copy the grid out (outside the lock: workers keep running)
+    // and free the device side.  The caller owns the finished request, so no
+    // other thread touches its context meanwhile.
+    gbees_ctx* c = r.ctx;
+    lk.unlock();
+    std::vector<CellRow> rows;
+    const int rc = host_cells(c, &rows);
+    lk.lock();
     if (rc != GBEES_OK) return rc;
+    r.rows = std::move(rows);
     r.exported = true;
     p->free_request(r);
   }

@@ -72,3 +72,26 @@ def test_init_rejects_bad_arguments_before_touching_the_device():
     assert L.gbees_init_gaussian(ctypes.byref(c), ctypes.c_void_p(1), 1 << 40, None, ctypes.byref(out)) == G.E_ARG
     assert L.gbees_step(None, 1.0, 0, None) == G.E_ARG
     assert L.gbees_destroy(None) == G.E_ARG
+
+
+def test_pool_struct_layout_and_argument_checks():
+    """Pool types match the header; calls reject bad arguments before any device work."""
+    assert ctypes.sizeof(G.GbeesMeas) == 8 + 4 + 4 + 8 + 8  # t, component (+pad), y, sigma
+    assert ctypes.sizeof(G.GbeesReqInfo) == 8 + 3 * 8 + 8 + 8 + ctypes.sizeof(G.GbeesStats)
+    L = G.lib()
+    out = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)
+    assert L.gbees_pool_create(None, 1 << 20, 4, ctypes.byref(out)) == G.E_ARG
+    assert L.gbees_pool_create(fake, 1 << 20, 0, ctypes.byref(out)) == G.E_ARG
+    assert L.gbees_pool_create(fake, 1 << 20, 257, ctypes.byref(out)) == G.E_ARG
+    assert L.gbees_pool_create(fake, 16, 4, ctypes.byref(out)) == G.E_ARG
+    c = G.make_config(S.l63_small(), max_cells=1 << 16)
+    rid = ctypes.c_int64(0)
+    assert L.gbees_pool_submit(None, ctypes.byref(c), 0.5, None, 0, ctypes.byref(rid)) == G.E_ARG
+    assert L.gbees_pool_progress(None, None, None) == G.E_ARG
+    assert L.gbees_pool_info(None, 1, None) == G.E_ARG
+    cnt = ctypes.c_int64(0)
+    assert L.gbees_pool_result(None, 1, 0, None, None, ctypes.byref(cnt)) == G.E_ARG
+    assert L.gbees_pool_release(None, 1) == G.E_ARG
+    assert L.gbees_pool_destroy(None) == G.E_ARG
+    assert L.gbees_pool_clock(None) == 0.0
