@@ -234,6 +234,18 @@ __device__ inline WaveRange wave_range(uint32_t n) {
   return WaveRange{lo + w, hi, per * kWavesPerWG};
 }
 
+// The same XCD split, in runs of kLanes consecutive bricks: the wave takes the
+// runs starting at begin, begin + step, ... below end.
+__device__ inline WaveRange wave_runs(uint32_t n) {
+  const uint32_t G = gridDim.x;
+  const uint32_t xcd = blockIdx.x & 7u, slot = blockIdx.x >> 3, per = G >> 3;
+  const uint32_t chunk = (n + 7u) / 8u;
+  const uint32_t lo = min(n, xcd * chunk), hi = min(n, lo + chunk);
+  const uint32_t w = slot * kWavesPerWG + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint64_t first = static_cast<uint64_t>(lo) + static_cast<uint64_t>(w) * kLanes;
+  return WaveRange{static_cast<uint32_t>(min<uint64_t>(first, hi)), hi, per * kWavesPerWG * kLanes};
+}
+
 // Contiguous chunk of [0, n) for this workgroup (stable-order compaction).
 __device__ inline void wg_chunk(uint64_t n, uint64_t& lo, uint64_t& hi) {
   const uint64_t G = gridDim.x;

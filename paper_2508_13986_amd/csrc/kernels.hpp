@@ -609,6 +609,20 @@ static __global__ void k_scan(uint32_t* part, uint32_t G, Scalars* sb, int gate,
 // ---------------------------------------------------------------------------
 // Grow (Sec. 3.3, Algorithm 2 semantics as set union over the pre-grow grid)
 // ---------------------------------------------------------------------------
+// S of this lane's cell in the brick with coordinates TB if the lane is one of
+// `created`, else 0.
+template <int N, int MODEL, typename Real>
+__device__ __forceinline__ double created_speed(const Dev<Real>& d, const int64_t* TB, u64 created, int lane) {
+  double s = 0.0;
+  if ((created >> lane) & 1ull) {
+    int32_t ii[N];
+    double xc[N];
+    cell_of<N>(d, TB, lane, ii, xc);
+    s = cell_speed<MODEL, N>(d, xc, ii);
+  }
+  return s;
+}
+
 // Adds the cells `bits` to the brick with coordinates TB (index tb, or kNone if
 // unknown).  Returns the largest S of the cells this call created (wave-uniform).
 template <int N, int MODEL, typename Real>
@@ -674,14 +688,7 @@ __device__ __forceinline__ double add_cells(const Dev<Real>& d, const int64_t* T
   const u64 created = bits & ~old;
   if (created == 0ull) return 0.0;
   *created_count += static_cast<u64>(__popcll(created));
-  double s = 0.0;
-  if ((created >> lane) & 1ull) {
-    int32_t ii[N];
-    double xc[N];
-    cell_of<N>(d, TB, lane, ii, xc);
-    s = cell_speed<MODEL, N>(d, xc, ii);
-  }
-  return wave_max(s);
+  return wave_max(created_speed<N, MODEL>(d, TB, created, lane));
 }
 
 template <typename Real>
@@ -725,14 +732,6 @@ __device__ __forceinline__ BrickMeta<N> meta_unpack(uint32_t v) {
   return r;
 }
 
-// Index of the brick at offset s e_j + r e_l from b through the link table (kNone if unknown).
-template <typename Real>
-__device__ __forceinline__ uint32_t diag_of(const Dev<Real>& d, uint32_t b, int j, int s, int l, int r) {
-  uint32_t t = nbr_of(d, nbr_of(d, b, j, s), l, r);
-  if (t == kNone) t = nbr_of(d, nbr_of(d, b, l, r), j, s);
-  return t;
-}
-
 // Targets of one brick: 0 = the brick itself, 1 + 2j + si = the axis neighbour
 // at s e_j (si = s > 0), then for each pair j < l and signs (s, r) the edge
 // neighbour at s e_j + r e_l.  Count: 1 + 2n + 4 n(n-1)/2.
@@ -760,16 +759,50 @@ __device__ __forceinline__ int target_kind(int k, int* j, int* s, int* l, int* r
   return 2;
 }
 
-// Lane-parallel resolution of target k of brick b: its index (kNone if not
-// reachable through the links) and the chosen per-brick word (mask or abv).
+// Axis links of brick b spread over the wave: lane 1 + 2j + si holds the index
+// of the brick at (si ? +1 : -1) e_j, every other lane kNone.
 template <int N, typename Real>
-__device__ __forceinline__ uint32_t resolve_target(const Dev<Real>& d, uint32_t b, int k) {
-  if (k >= n_targets(N)) return kNone;
+__device__ __forceinline__ uint32_t axis_links(const Dev<Real>& d, uint32_t b, int lane) {
+  return (lane >= 1 && lane < 1 + 2 * N) ? d.nbr[static_cast<size_t>(lane - 1) * d.cap_b + b] : kNone;
+}
+
+// Index of target k of brick b through the link table, kNone if the links do
+// not reach it (and for lanes whose `want` is false); axl holds b's axis links
+// (axis_links).  An edge target s e_j + r e_l is reached via the brick at s e_j,
+// else via the one at r e_l.  Axis targets and the first hop of edge targets
+// come from the axis lanes, so an edge target costs one link load, two when its
+// first route is missing.  Every lane of the wave must take part (the hops are
+// lane shuffles).
+template <int N, typename Real>
+__device__ __forceinline__ uint32_t resolve_target(const Dev<Real>& d, uint32_t b, int k, uint32_t axl, bool want) {
   int j = 0, s = 0, l = 0, r = 0;
-  const int kind = target_kind<N>(k, &j, &s, &l, &r);
+  const int kind = k < n_targets(N) ? target_kind<N>(k, &j, &s, &l, &r) : -1;
+  const uint32_t h1 = static_cast<uint32_t>(__shfl(static_cast<int>(axl), kind >= 1 ? 1 + 2 * j + (s > 0 ? 1 : 0) : 0));
+  const uint32_t h2 = static_cast<uint32_t>(__shfl(static_cast<int>(axl), kind == 2 ? 1 + 2 * l + (r > 0 ? 1 : 0) : 0));
+  if (!want || kind < 0) return kNone;
   if (kind == 0) return b;
-  if (kind == 1) return nbr_of(d, b, j, s);
-  return diag_of(d, b, j, s, l, r);
+  if (kind == 1) return h1;
+  uint32_t t = nbr_of(d, h1, l, r);
+  if (t == kNone) t = nbr_of(d, h2, j, s);
+  return t;
+}
+
+// A wave-uniform value moved to scalar registers.
+__device__ __forceinline__ double uniform(double v) {
+  const u64 b = double_to_bits(v);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(b));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(b >> 32));
+  return bits_to_double((static_cast<u64>(hi) << 32) | lo);
+}
+__device__ __forceinline__ float uniform(float v) {
+  return __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(v)));
+}
+
+// Orders this wave's LDS writes before its lanes read what other lanes wrote.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 __device__ __forceinline__ u64 readlane64(u64 v, int k) {
@@ -784,8 +817,11 @@ __device__ __forceinline__ uint32_t target_index(uint32_t t0, uint32_t t1, int k
   return k < 64 ? __builtin_amdgcn_readlane(t0, k) : __builtin_amdgcn_readlane(t1, k - 64);
 }
 
-// Four waves per SIMD: the scan is latency-bound (measured 12% faster than at
-// the three waves its register count would otherwise allow).
+// Bricks whose density rows are fetched together by the grow scan.
+constexpr int kGrowBatch = 8;
+
+// Four waves per SIMD (measured faster than the three its register count would
+// otherwise allow: the scan is bound by memory latency).
 template <int N, int MODEL, typename Real>
 __global__ __launch_bounds__(kWG, 4) void k_grow(Dev<Real> d) {
   Scalars* sb = d.sb;
@@ -793,43 +829,26 @@ __global__ __launch_bounds__(kWG, 4) void k_grow(Dev<Real> d) {
   const uint32_t nb_old = sb->nb_old;
   const Real* P = cur_p(d);
   const bool thr0 = !(d.thresh_rel > 0.0);
-  const Real pstar = static_cast<Real>(d.thresh_rel * sb->maxp);
+  // p* in scalar registers (a vector copy was spilled and reloaded per brick).
+  const Real pstar = uniform(static_cast<Real>(d.thresh_rel * sb->maxp));
   const int lane = lane_id();
   constexpr int NT = n_targets(N);
   __shared__ u64 tbl_all[kWavesPerWG][128];
+  __shared__ u64 work_all[kWavesPerWG][4 * kGrowBatch];
   u64* tbl = tbl_all[threadIdx.x >> 6];
+  u64* work = work_all[threadIdx.x >> 6];
   double smax = 0.0;
   u64 nscan = 0, ncreated = 0;
-  const WaveRange rg = wave_range(nb_old);
-  // Most bricks have no new source: fetch the next brick's mask, densities and
-  // done mask while the current one is processed, so the scan streams.
-  // A stale mask is harmless: cells added concurrently hold P = 0 and are no sources.
-  u64 m_next = 0ull, dn_next = 0ull;
-  Real p_next = Real(0);
-  if (rg.begin < rg.end) {
-    m_next = d.mask[rg.begin];
-    dn_next = d.done[rg.begin];
-    p_next = P[static_cast<size_t>(rg.begin) * kLanes + lane];
-  }
-  for (uint32_t b = rg.begin; b < rg.end; b += rg.step) {
-    const u64 m = m_next;
-    const u64 dn = dn_next;
-    const Real p0 = p_next;
-    const uint32_t bn = b + rg.step;
-    if (bn < rg.end) {
-      m_next = d.mask[bn];
-      dn_next = d.done[bn];
-      p_next = P[static_cast<size_t>(bn) * kLanes + lane];
-    }
-    const bool src = ((m >> lane) & 1ull) && (thr0 ? (p0 != Real(0)) : (p0 >= pstar));
-    const u64 S = ballot(src);
-    const u64 todo = S & ~dn;
-    if (todo == 0ull) continue;
+
+
+  // Grows brick b from its new sources `todo` (S: every source, dn: the done
+  // mask before this step, m: occupancy).
+  auto grow_brick = [&](uint32_t b, u64 m, u64 dn_new, u64 todo) {
     if (lane == 0) {
-      d.done[b] = dn | S;
+      d.done[b] = dn_new;
       ++nscan;
     }
-
+    const uint32_t axl = axis_links<N>(d, b, lane);
     int64_t B[N];
     unpack_key<N>(d.key[b], B);
     int32_t ii[N];
@@ -897,36 +916,111 @@ __global__ __launch_bounds__(kWG, 4) void k_grow(Dev<Real> d) {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const u64 bits0 = tbl[lane];
     const u64 bits1 = lane + 64 < NT ? tbl[lane + 64] : 0ull;
-    uint32_t t0 = kNone, t1 = kNone;
-    u64 need0 = 0ull, need1 = 0ull;
-    if (bits0 != 0ull) {
-      t0 = resolve_target<N>(d, b, lane);
-      need0 = bits0 & ~(t0 != kNone ? d.mask[t0] : 0ull);
-    }
-    if (bits1 != 0ull) {
-      t1 = resolve_target<N>(d, b, lane + 64);
-      need1 = bits1 & ~(t1 != kNone ? d.mask[t1] : 0ull);
-    }
-    u64 todo_t[2] = {ballot(need0 != 0ull), ballot(need1 != 0ull)};
+    const uint32_t t0 = resolve_target<N>(d, b, lane, axl, bits0 != 0ull);
+    const uint32_t t1 = resolve_target<N>(d, b, lane + 64, axl, bits1 != 0ull);
+    // Targets reached through the links take their cells with one atomicOr per
+    // lane, all in flight together; the cells each of them gained are then
+    // visited target by target for their S.  Targets without a link (a brick
+    // that does not exist yet, or one created during this step) go through the
+    // hashtable one at a time.
+    u64 made0 = 0ull, made1 = 0ull;
+    if (bits0 != 0ull && t0 != kNone) made0 = bits0 & ~atomicOr(&d.mask[t0], bits0);
+    if (bits1 != 0ull && t1 != kNone) made1 = bits1 & ~atomicOr(&d.mask[t1], bits1);
+    u64 made_t[2] = {ballot(made0 != 0ull), ballot(made1 != 0ull)};
+    u64 hash_t[2] = {ballot(bits0 != 0ull && t0 == kNone), ballot(bits1 != 0ull && t1 == kNone)};
+    auto target_brick = [&](int k, int64_t* TB) {
+      int j = 0, s = 0, l = 0, r = 0;
+      const int kind = target_kind<N>(k, &j, &s, &l, &r);
+      // Static indexes only: a runtime index would put TB in scratch memory.
+#pragma unroll
+      for (int q = 0; q < N; ++q) TB[q] = B[q] + (kind >= 1 && q == j ? s : 0) + (kind == 2 && q == l ? r : 0);
+    };
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
-      while (todo_t[half] != 0ull) {
-        const int kl = __builtin_ctzll(todo_t[half]);
-        todo_t[half] &= todo_t[half] - 1ull;
-        const int k = kl + 64 * half;
-        const u64 bits = readlane64(half ? bits1 : bits0, kl);
-        const uint32_t tk = __builtin_amdgcn_readlane(half ? t1 : t0, kl);
-        int j = 0, s = 0, l = 0, r = 0;
-        const int kind = target_kind<N>(k, &j, &s, &l, &r);
+      while (made_t[half] != 0ull) {
+        const int kl = __builtin_ctzll(made_t[half]);
+        made_t[half] &= made_t[half] - 1ull;
+        const u64 made = readlane64(half ? made1 : made0, kl);
         int64_t TB[N];
+        target_brick(kl + 64 * half, TB);
+        ncreated += static_cast<u64>(__popcll(made));
+        smax = fmax(smax, created_speed<N, MODEL>(d, TB, made, lane));
+      }
+      while (hash_t[half] != 0ull) {
+        const int kl = __builtin_ctzll(hash_t[half]);
+        hash_t[half] &= hash_t[half] - 1ull;
+        const u64 bits = readlane64(half ? bits1 : bits0, kl);
+        int64_t TB[N];
+        target_brick(kl + 64 * half, TB);
+        smax = fmax(smax, add_cells<N, MODEL>(d, TB, kNone, bits, lane, &ncreated));
+      }
+    }
+  };
+
+  // The scan takes runs of 64 bricks: lane i reads the occupancy and done masks
+  // of brick r + i, and only bricks holding a cell that has not yet been a
+  // source are candidates.  Their density rows are fetched kGrowBatch at a time
+  // so the round trips overlap; bricks with new sources are queued in LDS and
+  // grown one by one.  A stale mask is harmless: cells added concurrently hold
+  // P = 0 and are no sources.
+  const WaveRange rr = wave_runs(nb_old);
+  for (uint32_t r = rr.begin; r < rr.end; r += rr.step) {
+    const uint32_t bl = r + static_cast<uint32_t>(lane);
+    u64 ml = 0ull, dl = 0ull;
+    if (bl < rr.end) {
+      ml = d.mask[bl];
+      dl = d.done[bl];
+    }
+    u64 cand = ballot((ml & ~dl) != 0ull);
+    while (cand != 0ull) {
+      uint32_t bk[kGrowBatch];
+      u64 mk[kGrowBatch], dk[kGrowBatch];
+      Real pk[kGrowBatch];
 #pragma unroll
-        for (int q = 0; q < N; ++q) TB[q] = B[q];
-        if (kind >= 1) TB[j] += s;
-        if (kind == 2) TB[l] += r;
-        smax = fmax(smax, add_cells<N, MODEL>(d, TB, tk, bits, lane, &ncreated));
+      for (int k = 0; k < kGrowBatch; ++k) {
+        bk[k] = kNone;
+        mk[k] = dk[k] = 0ull;
+        pk[k] = Real(0);
+        if (cand != 0ull) {
+          const int kl = __builtin_ctzll(cand);
+          cand &= cand - 1ull;
+          bk[k] = r + static_cast<uint32_t>(kl);
+          mk[k] = readlane64(ml, kl);
+          dk[k] = readlane64(dl, kl);
+          pk[k] = P[static_cast<size_t>(bk[k]) * kLanes + lane];
+        }
+      }
+      int nwork = 0;
+#pragma unroll
+      for (int k = 0; k < kGrowBatch; ++k) {
+        if (bk[k] == kNone) break;
+        const bool src = ((mk[k] >> lane) & 1ull) && (thr0 ? (pk[k] != Real(0)) : (pk[k] >= pstar));
+        const u64 S = ballot(src);
+        const u64 todo = S & ~dk[k];
+        if (todo != 0ull) {
+          if (lane == 0) {
+            work[4 * nwork] = bk[k];
+            work[4 * nwork + 1] = mk[k];
+            work[4 * nwork + 2] = dk[k] | S;
+            work[4 * nwork + 3] = todo;
+          }
+          ++nwork;
+        }
+      }
+      if (nwork == 0) continue;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int w = 0; w < nwork; ++w) {
+        const uint32_t b = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<uint32_t>(work[4 * w])));
+        const u64 m = readlane64(work[4 * w + 1], 0);
+        const u64 dn_new = readlane64(work[4 * w + 2], 0);
+        const u64 todo = readlane64(work[4 * w + 3], 0);
+        grow_brick(b, m, dn_new, todo);
       }
     }
   }
+  smax = wave_max(smax);
   if (lane == 0 && smax > 0.0) atomicMax(&sb->smax_bits, double_to_bits(smax));
   if (lane == 0 && nscan > 0) atomicAdd(&sb->grow_bricks, nscan);
   if (lane == 0 && ncreated > 0) atomicAdd(&sb->inserted, ncreated);
@@ -1294,6 +1388,7 @@ __global__ __launch_bounds__(kWG) void k_prune_mark(Dev<Real> d) {
   for (uint32_t b = rg.begin; b < rg.end; b += rg.step) {
     const u64 m = d.mask[b];
     const u64 A = d.abv[b];
+    const uint32_t axl = axis_links<N>(d, b, lane);
     const u64 below = m & ~A;  // present cells with P < p*
     u64 keep = A;
     int64_t B[N];
@@ -1303,15 +1398,14 @@ __global__ __launch_bounds__(kWG) void k_prune_mark(Dev<Real> d) {
     cell_of<N>(d, B, lane, ii, xc);
     if (below != 0ull) {
       // Above-threshold lanes of every target brick, one target per lane.
-      uint32_t t0 = resolve_target<N>(d, b, lane), t1 = resolve_target<N>(d, b, lane + 64);
+      uint32_t t0 = resolve_target<N>(d, b, lane, axl, true);
+      uint32_t t1 = resolve_target<N>(d, b, lane + 64, axl, true);
       if (t0 == kNone && lane < n_targets(N)) {
         int j = 0, s = 0, l = 0, r = 0;
         if (target_kind<N>(lane, &j, &s, &l, &r) == 2) {
           int64_t TB[N];
 #pragma unroll
-          for (int q = 0; q < N; ++q) TB[q] = B[q];
-          TB[j] += s;
-          TB[l] += r;
+          for (int q = 0; q < N; ++q) TB[q] = B[q] + (q == j ? s : 0) + (q == l ? r : 0);
           if (brick_in_range<N>(TB)) t0 = hash_find(d, pack_key<N>(TB));
         }
       }
@@ -1320,9 +1414,7 @@ __global__ __launch_bounds__(kWG) void k_prune_mark(Dev<Real> d) {
         if (target_kind<N>(lane + 64, &j, &s, &l, &r) == 2) {
           int64_t TB[N];
 #pragma unroll
-          for (int q = 0; q < N; ++q) TB[q] = B[q];
-          TB[j] += s;
-          TB[l] += r;
+          for (int q = 0; q < N; ++q) TB[q] = B[q] + (q == j ? s : 0) + (q == l ? r : 0);
           if (brick_in_range<N>(TB)) t1 = hash_find(d, pack_key<N>(TB));
         }
       }
