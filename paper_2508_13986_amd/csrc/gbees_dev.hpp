@@ -356,10 +356,17 @@ template <int MODEL, int N, typename Real>
 __device__ __forceinline__ double face_vel(const Dev<Real>& d, const double* xc, const int32_t* ii, int j) {
   return drift_at<MODEL, N>(xc, j, face_coord(d.mean[j], ii[j], d.h[j]), d.params);
 }
+// face_coord(mean, i + 1, h), bit for bit: (i + 1) - 0.5 and i + 0.5 are the
+// same double for every int32 i, and this form reuses the conversion of i.
+__device__ __forceinline__ double face_coord_fwd(double mean, int32_t i, double h) {
+#pragma clang fp contract(off)
+  return mean + (static_cast<double>(i) + 0.5) * h;
+}
+
 // f_{i + 1/2 e_j, j}: velocity at the forward j-face (the backward face of i + e_j).
 template <int MODEL, int N, typename Real>
 __device__ __forceinline__ double face_vel_fwd(const Dev<Real>& d, const double* xc, const int32_t* ii, int j) {
-  return drift_at<MODEL, N>(xc, j, face_coord(d.mean[j], ii[j] + 1, d.h[j]), d.params);
+  return drift_at<MODEL, N>(xc, j, face_coord_fwd(d.mean[j], ii[j], d.h[j]), d.params);
 }
 
 // S_i = sum_j |f_{i - 1/2 e_j, j}| / h_j (Eq. 8).
