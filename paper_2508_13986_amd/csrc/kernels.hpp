@@ -1108,6 +1108,24 @@ __device__ __forceinline__ T load_const(const T* p) {
   return *(const __attribute__((address_space(4))) T*)(p);
 }
 
+// Cell widths and grid origin of a kernel whose first argument is `Dev<Real>`,
+// read again from the kernel arguments.  Called inside a loop, it costs a few
+// scalar loads (constant cache) per iteration; held across the loop, the values
+// are spilled from the full scalar register file and read back with one
+// vector-unit instruction per register on every use.
+template <typename Real>
+__device__ __forceinline__ void reload_geometry(Dev<Real>& g) {
+  const char* kp = (const char*)__builtin_amdgcn_kernarg_segment_ptr();
+  asm volatile("" : "+s"(kp));  // not hoisted out of the loop
+  const double* hp = reinterpret_cast<const double*>(kp + offsetof(Dev<Real>, h));
+  const double* mp = reinterpret_cast<const double*>(kp + offsetof(Dev<Real>, mean));
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    g.h[j] = load_const(hp + j);
+    g.mean[j] = load_const(mp + j);
+  }
+}
+
 // A wave-uniform value computed by vector instructions, moved to scalar
 // registers (keeps per-kernel constants out of the vector register file).
 __device__ __forceinline__ double to_sgpr(double v) {
@@ -1175,20 +1193,13 @@ __global__ __launch_bounds__(kWG, kFluxWavesPerEU) void k_flux_a(Dev<Real> d) {
 #pragma unroll
   for (int j = 0; j < N; ++j) c[j] = to_sgpr(static_cast<Real>(dt / (2.0 * d.h[j])));
   const int lane = lane_id();
-  // Cell widths and the grid origin as vector-register copies: the scalar
-  // file is full (links, neighbour masks), and reading them back from spilled
-  // scalars costs more than two vector registers each.
-  Dev<Real> dv = d;
-#pragma unroll
-  for (int j = 0; j < N; ++j) {
-    dv.h[j] = opaque(d.h[j]);
-    dv.mean[j] = opaque(d.mean[j]);
-  }
   const WaveRange rg = wave_range(nb);
   uint32_t meta = meta_fetch<N>(d, rg.begin < rg.end ? rg.begin : kNone, lane);
   for (uint32_t b = rg.begin; b < rg.end; b += rg.step) {
     const BrickMeta<N> bm = meta_unpack<N>(meta);
     const Real p0 = P[static_cast<size_t>(b) * kLanes + lane];
+    Dev<Real> dv = d;
+    reload_geometry(dv);
     // Only the face layer of each neighbour is needed: every lane loads the
     // neighbour cell of the boundary lane with its other coordinates.
     Real Fm[N], Fp[N];
@@ -1271,16 +1282,18 @@ __global__ __launch_bounds__(kWG, sizeof(Real) == 8 ? kFluxBWavesPerEU64 : kFlux
     const BrickMeta<N> bm = meta_unpack<N>(meta);
     const size_t o = static_cast<size_t>(b) * kLanes + lane;
     const Real p0 = P[o];
+    Dev<Real> dg = d;
+    reload_geometry(dg);
     int64_t B[N];
     unpack_key<N>(bm.key, B);
     int32_t ii[N];
     double xc[N];
-    cell_of<N>(d, B, lane, ii, xc);
+    cell_of<N>(dg, B, lane, ii, xc);
     Real ub[N], uf[N];
     static_for<N>([&](auto Lc) {
       constexpr int l = decltype(Lc)::value;
-      ub[l] = static_cast<Real>(face_vel<MODEL, N>(d, xc, ii, l));
-      uf[l] = static_cast<Real>(face_vel_fwd<MODEL, N>(d, xc, ii, l));
+      ub[l] = static_cast<Real>(face_vel<MODEL, N>(dg, xc, ii, l));
+      uf[l] = static_cast<Real>(face_vel_fwd<MODEL, N>(dg, xc, ii, l));
     });
     Real Pm[N], Pp[N], Qm[N], Qp[N];
     u64 mm[N], mp[N];
