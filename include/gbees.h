@@ -154,11 +154,15 @@ const char* gbees_strerror(int code);
  * a horizon and scalar measurements: the problem of Sec. 2 and 5.1 posed per
  * object) share one caller-owned device arena.  A request is admitted when a
  * slot is free and a slice of the arena of gbees_arena_bytes(cfg) bytes can be
- * carved out (so cfg->max_cells sets its footprint); admitted requests run
- * concurrently, each on its own stream, and leave the pool as soon as they
- * finish, which frees their slice for the next ones.  The pool allocates no
- * device memory; it owns one HIP stream, one event and one pinned scalar copy
- * per slot.  Times are seconds on the pool's monotonic clock.
+ * carved out (so cfg->max_cells sets its footprint).  Running requests of one
+ * kind (model, dimension, precision) are stepped together, one launch per
+ * kernel for all of them, by that kind's driver thread; each keeps its own
+ * device state and workgroup count and gets the result it would get alone.
+ * Requests leave the pool as soon as they finish, which frees their slot for
+ * the next ones (and their slice once the result was taken).  The pool
+ * allocates no device memory; it owns a HIP stream and an event per kind and a
+ * stream per admitted request.  Times are seconds on the pool's monotonic
+ * clock.
  * ---------------------------------------------------------------------- */
 typedef struct gbees_pool gbees_pool;
 
@@ -180,9 +184,9 @@ typedef struct {
 } gbees_req_info;
 
 /* arena: device buffer of arena_bytes owned by the caller for the pool's
- * life; max_active (1..256): requests running at once, each on one of the
- * pool's max_active worker threads.  All pool calls may come from any thread;
- * gbees_pool_result and gbees_pool_release of one request must not overlap. */
+ * life; max_active (1..256): requests running at once.  All pool calls may come
+ * from any thread; gbees_pool_result and gbees_pool_release of one request must
+ * not overlap. */
 int gbees_pool_create(void* arena, size_t arena_bytes, int32_t max_active, gbees_pool** out);
 
 /* Queue a request: initialise from the Gaussian of cfg (as gbees_init_gaussian),
@@ -193,11 +197,9 @@ int gbees_pool_create(void* arena, size_t arena_bytes, int32_t max_active, gbees
 int gbees_pool_submit(gbees_pool* pool, const gbees_config* cfg, double t_end, const gbees_meas* meas,
                       int32_t n_meas, int64_t* req);
 
-/* Advance the pool without waiting on the device: collect finished batches,
- * enqueue the next batch or correction of every running request, mark the
- * finished ones done (their slot is freed), admit waiting requests in arrival
- * order (looking up to three places past one that does not fit).  Either
- * count may be NULL. */
+/* Admit waiting requests in arrival order (looking up to three places past one
+ * that does not fit) to free slots and arena slices, without waiting on the
+ * device; the drivers run them.  Either count may be NULL. */
 int gbees_pool_progress(gbees_pool* pool, int32_t* n_running, int32_t* n_waiting);
 
 int gbees_pool_info(gbees_pool* pool, int64_t req, gbees_req_info* out);

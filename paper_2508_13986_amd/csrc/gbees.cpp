@@ -9,6 +9,7 @@
 #include <cmath>
 #include <condition_variable>
 #include <deque>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <cstring>
@@ -39,6 +40,7 @@ struct Layout {
   size_t hkey = 0, hval = 0;
   size_t ff_end = 0;
   size_t nbr = 0, Q = 0, defer = 0;
+  size_t devc = 0;  // device copy of the grid's Dev block (shared multi-grid launches read it)
   size_t total = 0;
 };
 
@@ -96,6 +98,8 @@ bool make_layout(const gbees_config& c, Layout* L) {
   L->nbr = take(2 * static_cast<size_t>(c.n) * cb * 4);
   L->Q = take(L->qbytes);
   L->defer = take(static_cast<size_t>(L->ndef) * 16);
+  static_assert(sizeof(gbees::Dev<double>) == sizeof(gbees::Dev<float>), "one Dev slot for both precisions");
+  L->devc = take(sizeof(gbees::Dev<double>));
   L->total = o;
   return true;
 }
@@ -260,6 +264,14 @@ struct gbees_ctx {
 
 namespace {
 
+// Copy the context's Dev block to its slot in the arena (read by launches that
+// serve several grids).  Call again after every change to the host copy; the
+// context must outlive the copy (it stays alive until its stream is synced).
+bool upload_dev(gbees_ctx* c) {
+  return hipMemcpyAsync(c->base + c->L.devc, c->dev, sizeof(gbees::Dev<double>), hipMemcpyHostToDevice, c->stream) ==
+         hipSuccess;
+}
+
 gbees_ctx* new_ctx(const gbees_config* cfg, void* arena, size_t bytes, void* stream, int* err) {
   *err = GBEES_E_ARG;
   if (!cfg || !arena) return nullptr;
@@ -281,7 +293,8 @@ gbees_ctx* new_ctx(const gbees_config* cfg, void* arena, size_t bytes, void* str
   }
   std::memset(&c->hsb, 0, sizeof(c->hsb));
   if (hipMemsetAsync(c->base, 0, L.zero_end, c->stream) != hipSuccess ||
-      hipMemsetAsync(c->base + L.zero_end, 0xFF, L.ff_end - L.zero_end, c->stream) != hipSuccess) {
+      hipMemsetAsync(c->base + L.zero_end, 0xFF, L.ff_end - L.zero_end, c->stream) != hipSuccess ||
+      !upload_dev(c)) {
     delete c;
     *err = GBEES_E_DEVICE;
     return nullptr;
@@ -296,6 +309,13 @@ void with_dev(gbees_ctx* c, F f) {
     f(c->d32);
   else
     f(c->d64);
+}
+
+// Delete a context whose stream may still hold work of new_ctx (clears and
+// the upload of its Dev block, which reads the context itself).
+void discard(gbees_ctx* c) {
+  hipStreamSynchronize(c->stream);
+  delete c;
 }
 
 int check_ctx(gbees_ctx* c) {
@@ -402,7 +422,7 @@ int init_gaussian_begin(const gbees_config* cfg, void* arena, size_t arena_bytes
     const int64_t blo = (-r >= 0) ? -r / side : -((r + side - 1) / side);
     const int64_t bhi = r / side;
     if (blo < -gbees::brick_limit(n) || bhi >= gbees::brick_limit(n)) {
-      delete c;
+      discard(c);
       return GBEES_E_RANGE;
     }
     lo[j] = blo;
@@ -410,7 +430,7 @@ int init_gaussian_begin(const gbees_config* cfg, void* arena, size_t arena_bytes
     box *= static_cast<double>(cnt[j]);
   }
   if (box > 4.0e12) {
-    delete c;
+    discard(c);
     return GBEES_E_ARG;
   }
   with_dev(c, [&](auto& d) {
@@ -427,6 +447,10 @@ int init_gaussian_begin(const gbees_config* cfg, void* arena, size_t arena_bytes
   uint64_t gb = (box_count + 63) / 64;
   gb = std::min<uint64_t>(std::max<uint64_t>((gb + 7) / 8 * 8, 8), gbees::kMaxWG);
   c->nb_est = static_cast<uint32_t>(std::min<uint64_t>(box_count, c->L.cap_b));
+  if (!upload_dev(c)) {
+    discard(c);
+    return GBEES_E_DEVICE;
+  }
   c->kt->init_gaussian(c->dev, c->stream, c->G(), static_cast<uint32_t>(gb));
   *out = c;
   return GBEES_OK;
@@ -449,7 +473,7 @@ int gbees_init_gaussian(const gbees_config* cfg, void* arena, size_t arena_bytes
   if (rc != GBEES_OK) return rc;
   rc = c->sync_read();
   if (rc != GBEES_OK) {
-    delete c;
+    discard(c);
     return rc;
   }
   *out = c;
@@ -472,14 +496,14 @@ int gbees_init_cells(const gbees_config* cfg, const int32_t* idx, const double* 
     bool ok;
     const u64 key = key_of_cell_n(n, idx + k * n, &ok);
     if (!ok) {
-      delete c;
+      discard(c);
       return GBEES_E_RANGE;
     }
     if (where.emplace(key, 0u).second) keys.push_back(key);
   }
   std::sort(keys.begin(), keys.end());
   if (keys.size() > c->L.cap_b) {
-    delete c;
+    discard(c);
     return GBEES_E_CAPACITY;
   }
   for (size_t b = 0; b < keys.size(); ++b) where[keys[b]] = static_cast<uint32_t>(b);
@@ -498,7 +522,7 @@ int gbees_init_cells(const gbees_config* cfg, const int32_t* idx, const double* 
       lane |= a << gbees::brick_off(n, j);
     }
     if ((mask[b] >> lane) & 1ull) {
-      delete c;
+      discard(c);
       return GBEES_E_ARG;  // duplicate cell
     }
     mask[b] |= 1ull << lane;
@@ -521,14 +545,14 @@ int gbees_init_cells(const gbees_config* cfg, const int32_t* idx, const double* 
   }
   okc = okc && hipMemcpyAsync(c->base + c->L.sb, &s0, sizeof(s0), hipMemcpyHostToDevice, c->stream) == hipSuccess;
   if (!okc) {
-    delete c;
+    discard(c);
     return GBEES_E_DEVICE;
   }
   c->nb_est = std::max<uint32_t>(s0.nb, 64);
   c->kt->init_finish(c->dev, c->stream, c->G());
   const int rc = c->sync_read();  // also keeps the host buffers alive until the copies finished
   if (rc != GBEES_OK) {
-    delete c;
+    discard(c);
     return rc;
   }
   *out = c;
@@ -731,12 +755,12 @@ const char* gbees_strerror(int code) {
 // ---------------------------------------------------------------------------
 // Serving pool: many propagation requests share one caller-owned arena.
 // Each admitted request gets a slice of the arena sized by its footprint
-// (gbees_arena_bytes of its configuration) and its own stream, and is run by
-// one of the pool's worker threads: initialise, step to each measurement
-// time, correct, step to the horizon, exactly as the single-grid calls do.
-// Worker threads enqueue in parallel, so requests overlap on the device and a
-// request whose stream queue is full blocks only its own thread.
-// gbees_pool_progress admits waiting requests in arrival order as workers and
+// (gbees_arena_bytes of its configuration) and runs through the same steps as
+// the single-grid calls: initialise, step to each measurement time, correct,
+// step to the horizon.  Running requests of one kind are stepped together by
+// their group's driver thread with shared launches (PoolGroup); requests of
+// different kinds overlap on the device through their groups' streams.
+// gbees_pool_progress admits waiting requests in arrival order as slots and
 // arena slices become free; it never waits on the device.
 // ---------------------------------------------------------------------------
 namespace {
@@ -795,59 +819,209 @@ struct PoolRequest {
   bool exported = false;
 };
 
-// Run one request to the end on its own stream (called by a worker thread,
-// which owns the request while its status is 1).
-int run_request(PoolRequest& r, char* base) {
-  gbees_ctx* c = nullptr;
-  int rc = init_gaussian_begin(&r.cfg, base + r.off, r.bytes, r.stream, &c);
-  if (rc != GBEES_OK) return rc;
-  r.ctx = c;
-  rc = c->sync_read();
-  for (size_t k = 0; rc == GBEES_OK && k <= r.meas.size(); ++k) {
-    const double target = k < r.meas.size() ? r.meas[k].t : r.t_end;
-    if (c->hsb.t < target) rc = gbees_step(c, target, 0, nullptr);
-    if (rc == GBEES_OK && k < r.meas.size())
-      rc = gbees_correct(c, r.meas[k].component, r.meas[k].y, r.meas[k].sigma);
-  }
-  if (rc == GBEES_OK) rc = gbees_get_stats(c, &r.stats);
-  return rc;
-}
+// A request's place in its group's run: the context, the next measurement
+// and the time it is stepping to.
+struct Runner {
+  int64_t id;
+  PoolRequest* r;
+  gbees_ctx* c;
+  size_t k;  // next measurement (k == meas.size(): stepping to t_end)
+  double target() const { return k < r->meas.size() ? r->meas[k].t : r->t_end; }
+};
 
 }  // namespace
 
+// Requests of one kind (model, dimension, precision) advance together: a
+// driver thread steps the running requests of its group with shared launches
+// (KernelTable::step_multi), so K steps of R grids cost 7K launches instead of
+// 7KR.  Each grid keeps its own workgroup count and device state, so it
+// computes exactly what it would compute alone; only the number of steps per
+// batch (the smallest any member asks for) is shared, and steps past a grid's
+// stop time are no-ops on the device.
+struct PoolGroup {
+  int model = 0, n = 0, precision = 0;
+  int members = 0;  // admitted and not finished (guarded by the pool mutex)
+  const gbees::KernelTable* kt = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t done_ev = nullptr;
+  std::deque<int64_t> inbox;  // admitted, not yet initialised (guarded by the pool mutex)
+  std::thread th;
+};
+
 struct gbees_pool {
+  // Requests per driver: enough to share launches, few enough that several
+  // drivers of one kind overlap on the device while one of them waits for its
+  // batch, reads back scalars or corrects.
+  static constexpr int kPerDriver = 4;
   char* base = nullptr;
   size_t total = 0;
   SliceAllocator slices{0};
   std::mutex mu;
   std::condition_variable work_cv;
-  std::deque<int64_t> pending;  // waiting for a worker and a slice
-  std::deque<int64_t> ready;    // admitted, waiting for a worker to pick up
+  std::deque<int64_t> pending;  // waiting for a slot and a slice
   std::unordered_map<int64_t, PoolRequest> reqs;
-  std::vector<std::thread> workers;
+  std::vector<std::unique_ptr<PoolGroup>> groups;
   int busy = 0, max_active = 0;
   bool stop = false;
   int64_t next_id = 1;
+  int device = 0;
   PoolClock::time_point t0 = PoolClock::now();
 
   double now() const { return std::chrono::duration<double>(PoolClock::now() - t0).count(); }
 
-  void worker() {
+  // The group of the request's kind with the fewest members, or a new one if
+  // each has kPerDriver.  (Caller holds mu.)
+  PoolGroup* group_for(const gbees_config& cfg) {
+    const int model = effective_model(cfg), prec = cfg.precision == 1 ? 1 : 0;
+    PoolGroup* best = nullptr;
+    for (auto& g : groups)
+      if (g->model == model && g->n == cfg.n && g->precision == prec && g->members < kPerDriver &&
+          (!best || g->members < best->members))
+        best = g.get();
+    if (best) return best;
+    auto g = std::make_unique<PoolGroup>();
+    g->model = model;
+    g->n = cfg.n;
+    g->precision = prec;
+    g->kt = gbees::kernel_table(model, cfg.n, prec);
+    if (!g->kt || hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&g->done_ev, hipEventDisableTiming) != hipSuccess) {
+      hipStreamDestroy(g->stream);
+      return nullptr;
+    }
+    PoolGroup* raw = g.get();
+    groups.push_back(std::move(g));
+    raw->th = std::thread([this, raw] { drive(*raw); });
+    return raw;
+  }
+
+  // Scalar blocks of every context in cs, with one wait on the group stream.
+  static int read_all(PoolGroup& g, const std::vector<gbees_ctx*>& cs) {
+    for (gbees_ctx* c : cs)
+      if (hipMemcpyAsync(&c->hsb, c->base + c->L.sb, sizeof(Scalars), hipMemcpyDeviceToHost, g.stream) != hipSuccess)
+        return GBEES_E_DEVICE;
+    if (hipStreamSynchronize(g.stream) != hipSuccess) return GBEES_E_DEVICE;
+    return GBEES_OK;
+  }
+
+  // A runner left its group (done or failed): hand its context over to the
+  // request's own stream, after everything the group stream holds for it.
+  void leave(PoolGroup& g, Runner& x, int rc) {
+    if (x.c) {
+      hipEventRecord(g.done_ev, g.stream);
+      hipStreamWaitEvent(x.r->stream, g.done_ev, 0);
+      x.c->stream = x.r->stream;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    x.r->t_done = now();
+    x.r->status = rc == GBEES_OK ? 2 : rc;
+    if (rc != GBEES_OK) free_request(*x.r);
+    --busy;
+    --g.members;
+  }
+
+  // Measurements due now (t reached), then the end: corrections and exits.
+  // Returns false when the runner is finished (left the group).
+  bool advance(PoolGroup& g, Runner& x) {
+    while (x.c->hsb.t >= x.target()) {
+      if (x.k == x.r->meas.size()) {
+        const int rc = gbees_get_stats(x.c, &x.r->stats);
+        leave(g, x, rc);
+        return false;
+      }
+      const gbees_meas& m = x.r->meas[x.k];
+      const int rc = gbees_correct(x.c, m.component, m.y, m.sigma);
+      if (rc != GBEES_OK) {
+        leave(g, x, rc);
+        return false;
+      }
+      ++x.k;
+    }
+    return true;
+  }
+
+  void drive(PoolGroup& g) {
     hipSetDevice(device);
-    std::unique_lock<std::mutex> lk(mu);
+    std::vector<Runner> run;
     while (true) {
-      work_cv.wait(lk, [&] { return stop || !ready.empty(); });
-      if (stop && ready.empty()) return;
-      const int64_t id = ready.front();
-      ready.pop_front();
-      PoolRequest& r = reqs[id];
-      lk.unlock();
-      const int rc = run_request(r, base);
-      lk.lock();
-      r.t_done = now();
-      r.status = rc == GBEES_OK ? 2 : rc;
-      if (rc != GBEES_OK) free_request(r);
-      --busy;
+      std::vector<int64_t> fresh;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        work_cv.wait(lk, [&] { return stop || !g.inbox.empty() || !run.empty(); });
+        if (stop && g.inbox.empty() && run.empty()) return;
+        fresh.assign(g.inbox.begin(), g.inbox.end());
+        g.inbox.clear();
+      }
+      // Initialise the newcomers on the group stream.
+      std::vector<Runner> born;
+      for (int64_t id : fresh) {
+        PoolRequest* r;
+        {
+          std::lock_guard<std::mutex> lk(mu);
+          r = &reqs[id];
+        }
+        Runner x{id, r, nullptr, 0};
+        const int rc = init_gaussian_begin(&r->cfg, base + r->off, r->bytes, g.stream, &x.c);
+        r->ctx = x.c;
+        if (rc != GBEES_OK) {
+          leave(g, x, rc);
+          continue;
+        }
+        born.push_back(x);
+      }
+      if (!born.empty()) {
+        std::vector<gbees_ctx*> cs;
+        for (auto& x : born) cs.push_back(x.c);
+        const int rc = read_all(g, cs);
+        for (auto& x : born) {
+          const int rx = rc != GBEES_OK ? rc : x.c->absorb();
+          if (rx != GBEES_OK)
+            leave(g, x, rx);
+          else if (advance(g, x))
+            run.push_back(x);
+        }
+      }
+      if (run.empty()) continue;
+      // One batch of K shared steps toward each runner's own target.
+      int K = 256;
+      for (auto& x : run) {
+        K = std::min(K, x.c->batch);
+        x.c->kt->set_tstop(x.c->dev, g.stream, x.target());
+      }
+      for (size_t at = 0; at < run.size(); at += gbees::kMultiMax) {
+        const size_t R = std::min<size_t>(gbees::kMultiMax, run.size() - at);
+        gbees::MultiGrids m{};
+        m.R = static_cast<uint32_t>(R);
+        m.wg0[0] = 0;
+        for (size_t i = 0; i < R; ++i) {
+          gbees_ctx* c = run[at + i].c;
+          m.dev[i] = c->base + c->L.devc;
+          m.wg0[i + 1] = m.wg0[i] + c->G();
+        }
+        for (int k = 0; k < K; ++k) {
+          g.kt->step_multi(m, g.stream);
+          for (size_t i = 0; i < R; ++i) {
+            gbees_ctx* c = run[at + i].c;
+            if (c->cfg.prune_every > 0 && ++c->host_steps % c->cfg.prune_every == 0)
+              c->kt->prune(c->dev, g.stream, c->G(), true, &c->prof);
+          }
+        }
+      }
+      std::vector<gbees_ctx*> cs;
+      for (auto& x : run) cs.push_back(x.c);
+      const int rc = read_all(g, cs);
+      std::vector<Runner> keep;
+      for (auto& x : run) {
+        const int rx = rc != GBEES_OK ? rc : x.c->absorb();
+        if (rx != GBEES_OK) {
+          leave(g, x, rx);
+          continue;
+        }
+        if (!advance(g, x)) continue;
+        x.c->adapt_batch(x.target());
+        keep.push_back(x);
+      }
+      run.swap(keep);
     }
   }
 
@@ -863,8 +1037,6 @@ struct gbees_pool {
       slices.give(r.off, r.bytes);
     }
   }
-
-  int device = 0;
 };
 
 extern "C" {
@@ -882,7 +1054,6 @@ int gbees_pool_create(void* arena, size_t arena_bytes, int32_t max_active, gbees
   p->total = arena_bytes / kAlign * kAlign;
   p->slices = SliceAllocator(p->total);
   p->max_active = max_active;
-  for (int k = 0; k < max_active; ++k) p->workers.emplace_back([p] { p->worker(); });
   *out = p;
   return GBEES_OK;
 }
@@ -929,7 +1100,8 @@ int gbees_pool_progress(gbees_pool* p, int32_t* n_running, int32_t* n_waiting) {
         ++it;
         continue;
       }
-      if (hipStreamCreateWithFlags(&r.stream, hipStreamNonBlocking) != hipSuccess) {
+      PoolGroup* g = p->group_for(r.cfg);
+      if (!g || hipStreamCreateWithFlags(&r.stream, hipStreamNonBlocking) != hipSuccess) {
         p->slices.give(off, r.bytes);
         r.stream = nullptr;
         rc = GBEES_E_DEVICE;
@@ -938,7 +1110,8 @@ int gbees_pool_progress(gbees_pool* p, int32_t* n_running, int32_t* n_waiting) {
       r.off = off;
       r.status = 1;
       r.t_admit = p->now();
-      p->ready.push_back(*it);
+      g->inbox.push_back(*it);
+      ++g->members;
       ++p->busy;
       ++admitted;
       it = p->pending.erase(it);
@@ -976,7 +1149,7 @@ int gbees_pool_result(gbees_pool* p, int64_t req, int64_t capacity, int32_t* idx
   if (r.status < 0) return r.status;
   if (r.status != 2) return GBEES_E_STATE;
   if (!r.exported) {
-    // First call: copy the grid out (outside the lock: workers keep running)
+    // First call: copy the grid out (outside the lock: the drivers keep running)
     // and free the device side.  The caller owns the finished request, so no
     // other thread touches its context meanwhile.
     gbees_ctx* c = r.ctx;
@@ -1022,8 +1195,12 @@ int gbees_pool_destroy(gbees_pool* p) {
     p->pending.clear();  // never admitted
   }
   p->work_cv.notify_all();
-  for (auto& t : p->workers) t.join();  // running requests finish first
+  for (auto& g : p->groups) g->th.join();  // running requests finish first
   for (auto& kv : p->reqs) p->free_request(kv.second);
+  for (auto& g : p->groups) {
+    hipEventDestroy(g->done_ev);
+    hipStreamDestroy(g->stream);
+  }
   delete p;
   return GBEES_OK;
 }

@@ -223,9 +223,18 @@ __device__ inline u64 double_to_bits(double v) { return static_cast<u64>(__doubl
 struct WaveRange {
   uint32_t begin, end, step;
 };
-__device__ inline WaveRange wave_range(uint32_t n) {
-  const uint32_t G = gridDim.x;
-  const uint32_t xcd = blockIdx.x & 7u, slot = blockIdx.x >> 3, per = G >> 3;
+// A workgroup's place in the launch that serves its grid: index wg of nwg.
+// A plain launch serves one grid with all its workgroups; a launch shared by
+// several grids gives each a contiguous run of workgroups whose length and
+// start are multiples of 8, so a workgroup's XCD is still wg % 8.
+struct Slot {
+  uint32_t wg, nwg;
+};
+__device__ inline Slot hw_slot() { return Slot{blockIdx.x, gridDim.x}; }
+
+__device__ inline WaveRange wave_range(uint32_t n, Slot sl) {
+  const uint32_t G = sl.nwg;
+  const uint32_t xcd = sl.wg & 7u, slot = sl.wg >> 3, per = G >> 3;
   const uint32_t chunk = (n + 7u) / 8u;
   const uint32_t lo = min(n, xcd * chunk), hi = min(n, lo + chunk);
   // readfirstlane tells the compiler the wave index is uniform, so brick-derived
@@ -233,17 +242,26 @@ __device__ inline WaveRange wave_range(uint32_t n) {
   const uint32_t w = slot * kWavesPerWG + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   return WaveRange{lo + w, hi, per * kWavesPerWG};
 }
+__device__ inline WaveRange wave_range(uint32_t n) { return wave_range(n, hw_slot()); }
 
-// The same XCD split, in runs of kLanes consecutive bricks: the wave takes the
-// runs starting at begin, begin + step, ... below end.
-__device__ inline WaveRange wave_runs(uint32_t n) {
-  const uint32_t G = gridDim.x;
-  const uint32_t xcd = blockIdx.x & 7u, slot = blockIdx.x >> 3, per = G >> 3;
+// The same XCD split, in runs of `len` consecutive bricks: the wave takes the
+// runs starting at begin, begin + step, ... below end.  Runs are up to 64 long
+// (one brick per lane) but no longer than the bricks per wave, so a small grid
+// still spreads over all waves.
+struct RunRange {
+  uint32_t begin, end, step, len;
+};
+__device__ inline RunRange wave_runs(uint32_t n, Slot sl) {
+  const uint32_t G = sl.nwg;
+  const uint32_t xcd = sl.wg & 7u, slot = sl.wg >> 3, per = G >> 3;
   const uint32_t chunk = (n + 7u) / 8u;
   const uint32_t lo = min(n, xcd * chunk), hi = min(n, lo + chunk);
   const uint32_t w = slot * kWavesPerWG + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const uint64_t first = static_cast<uint64_t>(lo) + static_cast<uint64_t>(w) * kLanes;
-  return WaveRange{static_cast<uint32_t>(min<uint64_t>(first, hi)), hi, per * kWavesPerWG * kLanes};
+  const uint32_t nw = per * kWavesPerWG;
+  uint32_t len = kLanes;
+  while (len > 1u && static_cast<uint64_t>(len) * nw > chunk) len >>= 1;
+  const uint64_t first = static_cast<uint64_t>(lo) + static_cast<uint64_t>(w) * len;
+  return RunRange{static_cast<uint32_t>(min<uint64_t>(first, hi)), hi, nw * len, len};
 }
 
 // Contiguous chunk of [0, n) for this workgroup (stable-order compaction).

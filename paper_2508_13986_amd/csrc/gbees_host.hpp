@@ -57,6 +57,17 @@ struct Profiler {
 
 // Launch sequences of one (model, dimension, precision) instantiation.  `dev`
 // points to a Dev<double> or Dev<float> matching the precision.
+// Grids of one kind stepped by shared launches: grid r owns workgroups
+// [wg0[r], wg0[r + 1]) of every grid-wide launch (a multiple of 8 each, the
+// count it would be launched with alone) and dev[r] is the device copy of its
+// Dev block.  Passed by value as the kernels' argument.
+constexpr int kMultiMax = 64;
+struct MultiGrids {
+  const void* dev[kMultiMax];
+  uint32_t wg0[kMultiMax + 1];
+  uint32_t R;
+};
+
 struct KernelTable {
   int n, model, precision;
   // Full initial grid from the ellipsoid box, then hashtable, links, speed, normalisation.
@@ -74,6 +85,9 @@ struct KernelTable {
   // Marginal: projected-key aggregation into a scratch table, compacted to [0, count).
   void (*marginals)(const void* dev, hipStream_t s, uint32_t G, uint32_t dim_mask, uint64_t table_mask);
   void (*probe)(const void* dev, hipStream_t s, uint32_t G, uint64_t n_miss, double* out2);
+  // One time step of every grid in m (each gated on its own device state), as
+  // `step` would take it alone with its own workgroup count.
+  void (*step_multi)(const MultiGrids& m, hipStream_t s);
 };
 
 const KernelTable* kernel_table(int model, int n, int precision);

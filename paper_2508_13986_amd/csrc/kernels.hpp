@@ -138,8 +138,8 @@ __device__ __forceinline__ Real hr_term(Real u, Real dth, Real w, Real wup) {
   return (w * wup > Real(0)) ? k * copysign(lim, w) : Real(0);
 }
 
-// Workgroup reduction of (max, sum, count) into dpart[blockIdx] (fixed order).
-__device__ inline void wg_store3(double vmax, double vsum, double vcnt, double* dpart) {
+// Workgroup reduction of (max, sum, count) into dpart[wg] (fixed order).
+__device__ inline void wg_store3(double vmax, double vsum, double vcnt, double* dpart, uint32_t wg) {
   __shared__ double sh[3][kWavesPerWG];
   vmax = wave_max(vmax);
   vsum = wave_sum(vsum);
@@ -158,9 +158,9 @@ __device__ inline void wg_store3(double vmax, double vsum, double vcnt, double* 
       b = b + sh[1][k];
       c = c + sh[2][k];
     }
-    dpart[blockIdx.x * kPartStride + 0] = a;
-    dpart[blockIdx.x * kPartStride + 1] = b;
-    dpart[blockIdx.x * kPartStride + 2] = c;
+    dpart[wg * kPartStride + 0] = a;
+    dpart[wg * kPartStride + 1] = b;
+    dpart[wg * kPartStride + 2] = c;
   }
 }
 
@@ -211,7 +211,7 @@ enum ScalarOp : int {
 };
 
 template <typename Real>
-__global__ void k_scalar(Dev<Real> d, int op, double arg) {
+__device__ __forceinline__ void scalar_op(const Dev<Real>& d, int op, double arg) {
   if (threadIdx.x != 0) return;
   Scalars* sb = d.sb;
   switch (op) {
@@ -269,10 +269,14 @@ __global__ void k_scalar(Dev<Real> d, int op, double arg) {
       break;
   }
 }
+template <typename Real>
+__global__ void k_scalar(Dev<Real> d, int op, double arg) {
+  scalar_op(d, op, arg);
+}
 
 // Commit the step: reductions of the updated densities, time, buffer flip.
 template <typename Real>
-__global__ void k_final_step(Dev<Real> d, uint32_t G) {
+__device__ __forceinline__ void final_step(const Dev<Real>& d, uint32_t G) {
   Scalars* sb = d.sb;
   if (!sb->run) return;
   double a, b, c;
@@ -288,6 +292,10 @@ __global__ void k_final_step(Dev<Real> d, uint32_t G) {
     sb->t = sb->t_next;
     sb->cur ^= 1u;
   }
+}
+template <typename Real>
+__global__ void k_final_step(Dev<Real> d, uint32_t G) {
+  final_step(d, G);
 }
 
 // mode 0: sum -> normaliser z = V * sum; mode 1: max -> maxp; mode 2: max, sum, count (stats)
@@ -352,9 +360,9 @@ __device__ __forceinline__ uint64_t neighbour_key(uint64_t key, int j, int s, bo
 // Link every brick in [lo, hi) to its 2n axis neighbours (thread per brick and direction);
 // with `both`, also point the neighbour back (used for bricks created this step).
 template <int N, typename Real>
-__device__ inline void link_range(const Dev<Real>& d, uint32_t lo, uint32_t hi, bool both) {
+__device__ inline void link_range(const Dev<Real>& d, uint32_t lo, uint32_t hi, bool both, Slot sl = hw_slot()) {
   const uint64_t total = static_cast<uint64_t>(hi - lo) * (2 * N);
-  for (uint64_t t = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; t < total; t += uint64_t(gridDim.x) * blockDim.x) {
+  for (uint64_t t = sl.wg * uint64_t(blockDim.x) + threadIdx.x; t < total; t += uint64_t(sl.nwg) * blockDim.x) {
     const uint32_t b = lo + static_cast<uint32_t>(t / (2 * N));
     const int dd = static_cast<int>(t % (2 * N));
     const int j = dd >> 1, s = (dd & 1) ? 1 : -1;
@@ -392,7 +400,7 @@ __global__ __launch_bounds__(kWG) void k_reduce(Dev<Real> d, int gate) {
       vcnt += 1.0;
     }
   }
-  wg_store3(vmax, vsum, vcnt, d.dpart);
+  wg_store3(vmax, vsum, vcnt, d.dpart, blockIdx.x);
 }
 
 // P <- P / z (z = V * sum P, Sec. 4.5 normalisation); partial max of the result.
@@ -419,7 +427,7 @@ __global__ __launch_bounds__(kWG) void k_scale(Dev<Real> d, int gate) {
       vcnt += 1.0;
     }
   }
-  wg_store3(vmax, vsum, vcnt, d.dpart);
+  wg_store3(vmax, vsum, vcnt, d.dpart, blockIdx.x);
 }
 
 // Bayesian correction (Eq. 4): P_i *= exp(-(y - x_i,c)^2 / (2 sigma^2)); partial max.
@@ -451,7 +459,7 @@ __global__ __launch_bounds__(kWG) void k_correct(Dev<Real> d, int comp, double y
       vcnt += 1.0;
     }
   }
-  wg_store3(vmax, vsum, vcnt, d.dpart);
+  wg_store3(vmax, vsum, vcnt, d.dpart, blockIdx.x);
 }
 
 // S over every cell of the grid (after initialisation).
@@ -823,7 +831,7 @@ constexpr int kGrowBatch = 8;
 // Four waves per SIMD (measured faster than the three its register count would
 // otherwise allow: the scan is bound by memory latency).
 template <int N, int MODEL, typename Real>
-__global__ __launch_bounds__(kWG, 4) void k_grow(Dev<Real> d) {
+__device__ __forceinline__ void grow_body(const Dev<Real>& d, Slot sl) {
   Scalars* sb = d.sb;
   if (!sb->run) return;
   const uint32_t nb_old = sb->nb_old;
@@ -957,17 +965,17 @@ __global__ __launch_bounds__(kWG, 4) void k_grow(Dev<Real> d) {
     }
   };
 
-  // The scan takes runs of 64 bricks: lane i reads the occupancy and done masks
-  // of brick r + i, and only bricks holding a cell that has not yet been a
+  // The scan takes runs of up to 64 bricks: lane i reads the occupancy and done
+  // masks of brick r + i, and only bricks holding a cell that has not yet been a
   // source are candidates.  Their density rows are fetched kGrowBatch at a time
   // so the round trips overlap; bricks with new sources are queued in LDS and
   // grown one by one.  A stale mask is harmless: cells added concurrently hold
   // P = 0 and are no sources.
-  const WaveRange rr = wave_runs(nb_old);
+  const RunRange rr = wave_runs(nb_old, sl);
   for (uint32_t r = rr.begin; r < rr.end; r += rr.step) {
     const uint32_t bl = r + static_cast<uint32_t>(lane);
     u64 ml = 0ull, dl = 0ull;
-    if (bl < rr.end) {
+    if (static_cast<uint32_t>(lane) < rr.len && bl < rr.end) {
       ml = d.mask[bl];
       dl = d.done[bl];
     }
@@ -1025,20 +1033,24 @@ __global__ __launch_bounds__(kWG, 4) void k_grow(Dev<Real> d) {
   if (lane == 0 && nscan > 0) atomicAdd(&sb->grow_bricks, nscan);
   if (lane == 0 && ncreated > 0) atomicAdd(&sb->inserted, ncreated);
 }
+template <int N, int MODEL, typename Real>
+__global__ __launch_bounds__(kWG, 4) void k_grow(Dev<Real> d) {
+  grow_body<N, MODEL, Real>(d, hw_slot());
+}
 
 // Link the bricks created this step and finish inserts that found their brick unpublished.
 template <int N, int MODEL, typename Real>
-__global__ __launch_bounds__(kWG) void k_grow_fix(Dev<Real> d) {
+__device__ __forceinline__ void grow_fix_body(const Dev<Real>& d, Slot sl) {
   Scalars* sb = d.sb;
   if (!sb->run || sb->status != 0) return;
   const uint32_t nb = min(sb->nb, d.cap_b), nb_old = sb->nb_old;
-  if (nb > nb_old) link_range<N>(d, nb_old, nb, true);
+  if (nb > nb_old) link_range<N>(d, nb_old, nb, true, sl);
   const uint32_t ndef = min(sb->ndeferred, d.ndef_cap);
   const int lane = lane_id();
   double smax = 0.0;
   u64 ncreated = 0;
-  const uint32_t wid = blockIdx.x * kWavesPerWG + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const uint32_t nw = gridDim.x * kWavesPerWG;
+  const uint32_t wid = sl.wg * kWavesPerWG + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t nw = sl.nwg * kWavesPerWG;
   for (uint32_t k = wid; k < ndef; k += nw) {
     const uint64_t hs = d.defer[2 * static_cast<size_t>(k)];
     const u64 bits = d.defer[2 * static_cast<size_t>(k) + 1];
@@ -1050,6 +1062,10 @@ __global__ __launch_bounds__(kWG) void k_grow_fix(Dev<Real> d) {
   }
   if (lane == 0 && smax > 0.0) atomicMax(&sb->smax_bits, double_to_bits(smax));
   if (lane == 0 && ncreated > 0) atomicAdd(&sb->inserted, ncreated);
+}
+template <int N, int MODEL, typename Real>
+__global__ __launch_bounds__(kWG) void k_grow_fix(Dev<Real> d) {
+  grow_fix_body<N, MODEL, Real>(d, hw_slot());
 }
 
 // ---------------------------------------------------------------------------
@@ -1108,14 +1124,21 @@ __device__ __forceinline__ T load_const(const T* p) {
   return *(const __attribute__((address_space(4))) T*)(p);
 }
 
-// Cell widths and grid origin of a kernel whose first argument is `Dev<Real>`,
-// read again from the kernel arguments.  Called inside a loop, it costs a few
-// scalar loads (constant cache) per iteration; held across the loop, the values
-// are spilled from the full scalar register file and read back with one
-// vector-unit instruction per register on every use.
+// The Dev block of a plain launch: its only argument, at the start of the
+// kernel-argument segment.
 template <typename Real>
-__device__ __forceinline__ void reload_geometry(Dev<Real>& g) {
-  const char* kp = (const char*)__builtin_amdgcn_kernarg_segment_ptr();
+__device__ __forceinline__ const Dev<Real>* kernarg_dev() {
+  return (const Dev<Real>*)__builtin_amdgcn_kernarg_segment_ptr();
+}
+
+// Cell widths and grid origin read again from the grid's Dev block (the
+// kernel arguments, or its copy in device memory).  Called inside a loop, it
+// costs a few scalar loads (constant cache) per iteration; held across the
+// loop, the values are spilled from the full scalar register file and read
+// back with one vector-unit instruction per register on every use.
+template <typename Real>
+__device__ __forceinline__ void reload_geometry(Dev<Real>& g, const Dev<Real>* src) {
+  const char* kp = reinterpret_cast<const char*>(src);
   asm volatile("" : "+s"(kp));  // not hoisted out of the loop
   const double* hp = reinterpret_cast<const double*>(kp + offsetof(Dev<Real>, h));
   const double* mp = reinterpret_cast<const double*>(kp + offsetof(Dev<Real>, mean));
@@ -1182,7 +1205,7 @@ __device__ __forceinline__ void q_from_t(Real p0, const Real* c, const Real* T, 
 
 // Flux pass A: transverse fluctuations and corrected states Q_l.
 template <int N, int MODEL, typename Real>
-__global__ __launch_bounds__(kWG, kFluxWavesPerEU) void k_flux_a(Dev<Real> d) {
+__device__ __forceinline__ void flux_a_body(const Dev<Real>& d, const Dev<Real>* dsrc, Slot sl) {
   const Scalars* sb = d.sb;
   // The scalar block is written only between passes: read it as constant.
   if (!load_const(&sb->run)) return;
@@ -1193,13 +1216,13 @@ __global__ __launch_bounds__(kWG, kFluxWavesPerEU) void k_flux_a(Dev<Real> d) {
 #pragma unroll
   for (int j = 0; j < N; ++j) c[j] = to_sgpr(static_cast<Real>(dt / (2.0 * d.h[j])));
   const int lane = lane_id();
-  const WaveRange rg = wave_range(nb);
+  const WaveRange rg = wave_range(nb, sl);
   uint32_t meta = meta_fetch<N>(d, rg.begin < rg.end ? rg.begin : kNone, lane);
   for (uint32_t b = rg.begin; b < rg.end; b += rg.step) {
     const BrickMeta<N> bm = meta_unpack<N>(meta);
     const Real p0 = P[static_cast<size_t>(b) * kLanes + lane];
     Dev<Real> dv = d;
-    reload_geometry(dv);
+    reload_geometry(dv, dsrc);
     // Only the face layer of each neighbour is needed: every lane loads the
     // neighbour cell of the boundary lane with its other coordinates.
     Real Fm[N], Fp[N];
@@ -1254,10 +1277,14 @@ __global__ __launch_bounds__(kWG, kFluxWavesPerEU) void k_flux_a(Dev<Real> d) {
     });
   }
 }
+template <int N, int MODEL, typename Real>
+__global__ __launch_bounds__(kWG, kFluxWavesPerEU) void k_flux_a(Dev<Real> d) {
+  flux_a_body<N, MODEL, Real>(d, kernarg_dev<Real>(), hw_slot());
+}
 
 // Flux pass B: face fluxes, high-resolution term, conservative update.
 template <int N, int MODEL, typename Real>
-__global__ __launch_bounds__(kWG, sizeof(Real) == 8 ? kFluxBWavesPerEU64 : kFluxBWavesPerEU32) void k_flux_b(Dev<Real> d) {
+__device__ __forceinline__ void flux_b_body(const Dev<Real>& d, const Dev<Real>* dsrc, Slot sl) {
   const Scalars* sb = d.sb;
   // The scalar block is written only between passes: read it as constant.
   if (!load_const(&sb->run)) return;
@@ -1276,14 +1303,14 @@ __global__ __launch_bounds__(kWG, sizeof(Real) == 8 ? kFluxBWavesPerEU64 : kFlux
   const int lane = lane_id();
   double vmax = 0.0, vsum = 0.0;
   uint32_t ncells = 0;  // wave-uniform
-  const WaveRange rg = wave_range(nb);
+  const WaveRange rg = wave_range(nb, sl);
   uint32_t meta = meta_fetch<N>(d, rg.begin < rg.end ? rg.begin : kNone, lane);
   for (uint32_t b = rg.begin; b < rg.end; b += rg.step) {
     const BrickMeta<N> bm = meta_unpack<N>(meta);
     const size_t o = static_cast<size_t>(b) * kLanes + lane;
     const Real p0 = P[o];
     Dev<Real> dg = d;
-    reload_geometry(dg);
+    reload_geometry(dg, dsrc);
     int64_t B[N];
     unpack_key<N>(bm.key, B);
     int32_t ii[N];
@@ -1370,7 +1397,73 @@ __global__ __launch_bounds__(kWG, sizeof(Real) == 8 ? kFluxBWavesPerEU64 : kFlux
     vsum += static_cast<double>(out);
     ncells += static_cast<uint32_t>(__builtin_popcountll(bm.mask));
   }
-  wg_store3(vmax, vsum, lane == 0 ? static_cast<double>(ncells) : 0.0, d.dpart);
+  wg_store3(vmax, vsum, lane == 0 ? static_cast<double>(ncells) : 0.0, d.dpart, sl.wg);
+}
+template <int N, int MODEL, typename Real>
+__global__ __launch_bounds__(kWG, sizeof(Real) == 8 ? kFluxBWavesPerEU64 : kFluxBWavesPerEU32) void k_flux_b(Dev<Real> d) {
+  flux_b_body<N, MODEL, Real>(d, kernarg_dev<Real>(), hw_slot());
+}
+
+// ---------------------------------------------------------------------------
+// One time step of several grids per launch (MultiGrids): workgroup w serves
+// the grid whose run [wg0[r], wg0[r + 1]) holds it, with that grid's own
+// workgroup index and count, so every grid computes exactly what its plain
+// launches compute.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t multi_grid(const MultiGrids& m, uint32_t w) {
+  uint32_t r = 0;
+  while (r + 1 < m.R && m.wg0[r + 1] <= w) ++r;
+  return r;
+}
+// Grid r's Dev block, read through the constant address space: the copy in
+// device memory never changes while kernels run, and saying so lets its fields
+// live in scalar registers like kernel arguments.
+template <typename Real>
+__device__ __forceinline__ Dev<Real> multi_dev(const MultiGrids& m, uint32_t r) {
+  static_assert(sizeof(Dev<Real>) % 8 == 0, "Dev is copied in 8-byte words");
+  constexpr int kWords = sizeof(Dev<Real>) / 8;
+  const u64* src = static_cast<const u64*>(m.dev[r]);
+  u64 w[kWords];
+#pragma unroll
+  for (int k = 0; k < kWords; ++k) w[k] = load_const(src + k);  // unused words are never loaded
+  Dev<Real> d;
+  __builtin_memcpy(&d, w, sizeof(d));
+  return d;
+}
+__device__ __forceinline__ Slot multi_slot(const MultiGrids& m, uint32_t r) {
+  return Slot{blockIdx.x - m.wg0[r], m.wg0[r + 1] - m.wg0[r]};
+}
+
+// One workgroup per grid.
+template <typename Real>
+__global__ void k_scalar_multi(MultiGrids m, int op) {
+  scalar_op(multi_dev<Real>(m, blockIdx.x), op, 0.0);
+}
+template <typename Real>
+__global__ void k_final_step_multi(MultiGrids m) {
+  final_step(multi_dev<Real>(m, blockIdx.x), m.wg0[blockIdx.x + 1] - m.wg0[blockIdx.x]);
+}
+// wg0[R] workgroups.
+template <int N, int MODEL, typename Real>
+__global__ __launch_bounds__(kWG, 4) void k_grow_multi(MultiGrids m) {
+  const uint32_t r = multi_grid(m, blockIdx.x);
+  grow_body<N, MODEL, Real>(multi_dev<Real>(m, r), multi_slot(m, r));
+}
+template <int N, int MODEL, typename Real>
+__global__ __launch_bounds__(kWG) void k_grow_fix_multi(MultiGrids m) {
+  const uint32_t r = multi_grid(m, blockIdx.x);
+  grow_fix_body<N, MODEL, Real>(multi_dev<Real>(m, r), multi_slot(m, r));
+}
+template <int N, int MODEL, typename Real>
+__global__ __launch_bounds__(kWG, kFluxWavesPerEU) void k_flux_a_multi(MultiGrids m) {
+  const uint32_t r = multi_grid(m, blockIdx.x);
+  flux_a_body<N, MODEL, Real>(multi_dev<Real>(m, r), static_cast<const Dev<Real>*>(m.dev[r]), multi_slot(m, r));
+}
+template <int N, int MODEL, typename Real>
+__global__ __launch_bounds__(kWG, sizeof(Real) == 8 ? kFluxBWavesPerEU64 : kFluxBWavesPerEU32) void k_flux_b_multi(
+    MultiGrids m) {
+  const uint32_t r = multi_grid(m, blockIdx.x);
+  flux_b_body<N, MODEL, Real>(multi_dev<Real>(m, r), static_cast<const Dev<Real>*>(m.dev[r]), multi_slot(m, r));
 }
 
 // ---------------------------------------------------------------------------
@@ -1854,6 +1947,18 @@ struct Ops {
     k_final_step<Real><<<1, kWG, 0, s>>>(d, G);
   }
 
+  static void step_multi(const MultiGrids& m, hipStream_t s) {
+    if (m.R == 0) return;
+    const uint32_t W = m.wg0[m.R];
+    k_scalar_multi<Real><<<m.R, 64, 0, s>>>(m, kOpStepBegin);
+    k_grow_multi<N, MODEL, Real><<<W, kWG, 0, s>>>(m);
+    k_grow_fix_multi<N, MODEL, Real><<<W, kWG, 0, s>>>(m);
+    k_scalar_multi<Real><<<m.R, 64, 0, s>>>(m, kOpDt);
+    k_flux_a_multi<N, MODEL, Real><<<W, kWG, 0, s>>>(m);
+    k_flux_b_multi<N, MODEL, Real><<<W, kWG, 0, s>>>(m);
+    k_final_step_multi<Real><<<m.R, kWG, 0, s>>>(m);
+  }
+
   static void prune(const void* p, hipStream_t s, uint32_t G, bool from_step, Profiler* pf) {
     const Dev<Real>& d = D(p);
     pf->begin(kProfPrune, s);
@@ -1900,7 +2005,8 @@ struct Ops {
 
   static const KernelTable* table(int prec) {
     static const KernelTable t = {N,          MODEL,   prec,      &init_gaussian, &init_finish, &step,
-                                  &prune,     &correct, &normalise, &set_tstop,     &marginals,   &probe};
+                                  &prune,     &correct, &normalise, &set_tstop,     &marginals,   &probe,
+                                  &step_multi};
     return &t;
   }
 };

@@ -86,6 +86,24 @@ def test_pool_results_equal_alone(G):
     pool.close()
 
 
+def test_pool_group_of_eight_equal_alone(G):
+    """Eight Lorenz-63 requests (different cell sizes, horizons and
+    measurements) stepped together by shared launches: each result equals the
+    request run alone."""
+    reqs, _ = S.serving_requests(64)
+    reqs = [r for r in reqs if r["n"] == 3][:8]
+    assert len(reqs) == 8 and len({(r["h"][0], r["t_end"]) for r in reqs}) > 1
+    ref = [alone(G, r) for r in reqs]
+    pool = G.Pool(sum(G.arena_bytes(r, cap(r)) for r in reqs) + (1 << 20), max_active=8)
+    ids = [pool.submit(r, cap(r)) for r in reqs]
+    out = drain(pool, ids)
+    for k, rid in enumerate(ids):
+        assert out[rid][0]["status"] == 2
+        assert_same(out[rid][1], ref[k], f"request {k}")
+        pool.release(rid)
+    pool.close()
+
+
 def test_pool_admits_by_footprint(G):
     """An arena that holds one request at a time: requests run one after the
     other even with free slots, and their results are unchanged."""
