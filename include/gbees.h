@@ -160,8 +160,8 @@ const char* gbees_strerror(int code);
  * device state and workgroup count and gets the result it would get alone.
  * Requests leave the pool as soon as they finish, which frees their slot for
  * the next ones (and their slice once the result was taken).  The pool
- * allocates no device memory; it owns a HIP stream and an event per kind and a
- * stream per admitted request.  Times are seconds on the pool's monotonic
+ * allocates no device memory; it owns a HIP stream per group of requests and
+ * one per admitted request.  Times are seconds on the pool's monotonic
  * clock.
  * ---------------------------------------------------------------------- */
 typedef struct gbees_pool gbees_pool;

@@ -843,7 +843,6 @@ struct PoolGroup {
   int members = 0;  // admitted and not finished (guarded by the pool mutex)
   const gbees::KernelTable* kt = nullptr;
   hipStream_t stream = nullptr;
-  hipEvent_t done_ev = nullptr;
   std::deque<int64_t> inbox;  // admitted, not yet initialised (guarded by the pool mutex)
   std::thread th;
 };
@@ -885,10 +884,6 @@ struct gbees_pool {
     g->precision = prec;
     g->kt = gbees::kernel_table(model, cfg.n, prec);
     if (!g->kt || hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking) != hipSuccess) return nullptr;
-    if (hipEventCreateWithFlags(&g->done_ev, hipEventDisableTiming) != hipSuccess) {
-      hipStreamDestroy(g->stream);
-      return nullptr;
-    }
     PoolGroup* raw = g.get();
     groups.push_back(std::move(g));
     raw->th = std::thread([this, raw] { drive(*raw); });
@@ -904,14 +899,13 @@ struct gbees_pool {
     return GBEES_OK;
   }
 
-  // A runner left its group (done or failed): hand its context over to the
-  // request's own stream, after everything the group stream holds for it.
+  // A runner left its group (done or failed): its context moves to the
+  // request's own stream for the export and release.  Every exit comes right
+  // after a wait on the group stream (the batch read-back, a correction or the
+  // final statistics), so no group work for this grid is still pending.
   void leave(PoolGroup& g, Runner& x, int rc) {
-    if (x.c) {
-      hipEventRecord(g.done_ev, g.stream);
-      hipStreamWaitEvent(x.r->stream, g.done_ev, 0);
-      x.c->stream = x.r->stream;
-    }
+    if (rc != GBEES_OK) (void)hipStreamSynchronize(g.stream);  // an error may have cut a wait short
+    if (x.c) x.c->stream = x.r->stream;
     std::lock_guard<std::mutex> lk(mu);
     x.r->t_done = now();
     x.r->status = rc == GBEES_OK ? 2 : rc;
@@ -1197,10 +1191,7 @@ int gbees_pool_destroy(gbees_pool* p) {
   p->work_cv.notify_all();
   for (auto& g : p->groups) g->th.join();  // running requests finish first
   for (auto& kv : p->reqs) p->free_request(kv.second);
-  for (auto& g : p->groups) {
-    hipEventDestroy(g->done_ev);
-    hipStreamDestroy(g->stream);
-  }
+  for (auto& g : p->groups) hipStreamDestroy(g->stream);
   delete p;
   return GBEES_OK;
 }
