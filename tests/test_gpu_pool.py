@@ -104,6 +104,22 @@ def test_pool_group_of_eight_equal_alone(G):
     pool.close()
 
 
+def test_pool_fp32_group_equal_alone(G):
+    """The FP32 form through shared launches: three Lorenz-63 requests with
+    FP32 densities in one group give the FP32 path's result alone."""
+    reqs, _ = S.serving_requests(64)
+    reqs = [dict(r, precision=1) for r in reqs if r["n"] == 3][:3]
+    ref = [alone(G, r) for r in reqs]
+    pool = G.Pool(sum(G.arena_bytes(r, cap(r)) for r in reqs) + (1 << 20), max_active=3)
+    ids = [pool.submit(r, cap(r)) for r in reqs]
+    out = drain(pool, ids)
+    for k, rid in enumerate(ids):
+        assert out[rid][0]["status"] == 2
+        assert_same(out[rid][1], ref[k], f"fp32 request {k}")
+        pool.release(rid)
+    pool.close()
+
+
 def test_pool_admits_by_footprint(G):
     """An arena that holds one request at a time: requests run one after the
     other even with free slots, and their results are unchanged."""
