@@ -138,6 +138,26 @@ def test_pool_admits_by_footprint(G):
     pool.close()
 
 
+def test_pool_group_survives_a_failing_member(G):
+    """A group member whose grid does not fit its capacity (here already the
+    initial grid) fails alone: the other members of its group finish with the
+    results they get alone."""
+    reqs, _ = S.serving_requests(64)
+    reqs = [r for r in reqs if r["n"] == 3][:3]
+    caps = [cap(reqs[0]), 64 * 16, cap(reqs[2])]  # the middle one outgrows 16 bricks
+    ref = {0: alone(G, reqs[0]), 2: alone(G, reqs[2])}
+    pool = G.Pool(sum(G.arena_bytes(r, c) for r, c in zip(reqs, caps)) + (1 << 20), max_active=3)
+    ids = [pool.submit(r, c) for r, c in zip(reqs, caps)]
+    out = drain(pool, ids)
+    assert out[ids[1]][0]["status"] == G.E_CAPACITY
+    for k in (0, 2):
+        assert out[ids[k]][0]["status"] == 2
+        assert_same(out[ids[k]][1], ref[k], f"request {k}")
+    for rid in ids:
+        pool.release(rid)
+    pool.close()
+
+
 def test_pool_error_paths(G):
     reqs = small_requests(2)
     r = reqs[0]
