@@ -76,12 +76,24 @@ def l96_6d_downsampled(seed=3):
     return l96_6d(h=0.5, thresh_rel=1e-5, seed=seed)
 
 
+def l63_paper(thresh_rel=1e-5):
+    """The paper's Lorenz '63 case (Sec. 5.1.1): (sigma, b, r) = (4, 1, 48) in
+    its shifted form (standard form with rho = r and z_shift = r), mean
+    (-11.5, -10, 9.5), unit variances, h = 0.5, a measurement y = x3 = -8 with
+    sigma_y = 1 at t = 1, horizon 2.  The threshold is not stated (read as 1e-5)."""
+    d = _base(3, L63, lorenz63(sigma=4.0, rho=48.0, beta=1.0, z_shift=48.0), 0.5, [-11.5, -10.0, 9.5],
+              np.eye(3), thresh_rel, 2.0)
+    d["measurements"] = [(1.0, 2, -8.0, 1.0)]
+    return d
+
+
 WORKLOADS = {
     "l63_small": l63_small,
     "l63_corrections": l63_corrections,
     "l96_6d": l96_6d,
     "l96_6d_fp32": l96_6d_fp32,
     "l96_6d_downsampled": l96_6d_downsampled,
+    "l63_paper": l63_paper,
 }
 
 
