@@ -201,7 +201,7 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true", help="skip the FP32-form error report")
     ap.add_argument("--requests", type=int, default=256, help="serving: requests in the stream")
     ap.add_argument("--load", type=float, default=2.0, help="serving: offered load rho = lambda * E[service]")
-    ap.add_argument("--max-active", type=int, default=16, help="serving: requests running at once")
+    ap.add_argument("--max-active", type=int, default=48, help="serving: requests running at once")
     ap.add_argument("--pool-gib", type=float, default=160.0, help="serving: arena of the pool")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
