@@ -245,9 +245,12 @@ __device__ inline WaveRange wave_range(uint32_t n, Slot sl) {
 __device__ inline WaveRange wave_range(uint32_t n) { return wave_range(n, hw_slot()); }
 
 // The same XCD split, in runs of `len` consecutive bricks: the wave takes the
-// runs starting at begin, begin + step, ... below end.  Runs are up to 64 long
-// (one brick per lane) but no longer than the bricks per wave, so a small grid
-// still spreads over all waves.
+// runs starting at begin, begin + step, ... below end.  Runs are up to kRunMax
+// long but no longer than the bricks per wave, so a small grid still spreads
+// over all waves.  Bricks that need work cluster in the Morton order, and
+// short runs deal them out more evenly: 16 measured fastest (64: 4% slower,
+// 4: 4%, 2: 12%).
+constexpr uint32_t kRunMax = 16;
 struct RunRange {
   uint32_t begin, end, step, len;
 };
@@ -258,7 +261,7 @@ __device__ inline RunRange wave_runs(uint32_t n, Slot sl) {
   const uint32_t lo = min(n, xcd * chunk), hi = min(n, lo + chunk);
   const uint32_t w = slot * kWavesPerWG + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t nw = per * kWavesPerWG;
-  uint32_t len = kLanes;
+  uint32_t len = kRunMax;
   while (len > 1u && static_cast<uint64_t>(len) * nw > chunk) len >>= 1;
   const uint64_t first = static_cast<uint64_t>(lo) + static_cast<uint64_t>(w) * len;
   return RunRange{static_cast<uint32_t>(min<uint64_t>(first, hi)), hi, nw * len, len};

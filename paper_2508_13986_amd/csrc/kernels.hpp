@@ -965,8 +965,8 @@ __device__ __forceinline__ void grow_body(const Dev<Real>& d, Slot sl) {
     }
   };
 
-  // The scan takes runs of up to 64 bricks: lane i reads the occupancy and done
-  // masks of brick r + i, and only bricks holding a cell that has not yet been a
+  // The scan takes runs of up to kRunMax bricks: lane i reads the occupancy and
+  // done masks of brick r + i, and only bricks holding a cell that has not yet been a
   // source are candidates.  Their density rows are fetched kGrowBatch at a time
   // so the round trips overlap; bricks with new sources are queued in LDS and
   // grown one by one.  A stale mask is harmless: cells added concurrently hold
