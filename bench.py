@@ -210,7 +210,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (see the design notes on sharding)",
+        print("bench.py runs on one GPU only: there is no multi-GPU path (requests or Morton ranges would be sharded; not implemented)",
               file=sys.stderr)
         sys.exit(2)
 
