@@ -67,18 +67,7 @@ struct IdxHash {
   }
 };
 
-struct Face {
-  Idx i;  // the face is the backward face of cell i in dimension j
-  int j;
-  bool operator==(const Face& o) const { return j == o.j && i == o.i; }
-};
-
-struct FaceHash {
-  size_t operator()(const Face& f) const { return IdxHash()(f.i) * 31u + static_cast<size_t>(f.j); }
-};
-
 using Grid = std::unordered_map<Idx, double, IdxHash>;
-using FaceMap = std::unordered_map<Face, double, FaceHash>;
 
 }  // namespace
 
@@ -346,31 +335,53 @@ struct Oracle {
     return w > 0.0 ? m : -m;
   }
 
-  void fluxes(double dt, FaceMap& F) const {
+  // Face fluxes of one step.  Only a face whose two cells are both in the grid
+  // enters the update (R1), and such a face is the backward face of a grid
+  // cell, so the fluxes are kept per grid cell: F[i][j] is the flux through the
+  // face between i - e_j and i.  Contributions to faces of cells outside the
+  // grid are dropped.
+  using FluxMap = std::unordered_map<Idx, std::array<double, kMaxDim>, IdxHash>;
+
+  static void add_flux(FluxMap& F, const Idx& c, int j, double v) {
+    auto it = F.find(c);
+    if (it != F.end()) it->second[j] += v;
+  }
+
+  void fluxes(double dt, FluxMap& F) const {
     const int nn = n();
-    // Donor Cell Upwind flux at every backward face of every cell (Eq. 7).
+    // Donor Cell Upwind (Eq. 7): the flux through each backward face carries
+    // the density of the cell the face velocity comes from.
     for (const auto& kv : grid) {
       const Idx& i = kv.first;
+      std::array<double, kMaxDim> f{};
       for (int j = 0; j < nn; ++j) {
         const double u = face_vel(i, j);
-        F[Face{i, j}] = pos(u) * P(shift(i, j, -1)) + neg(u) * kv.second;
+        f[j] = pos(u) * P(shift(i, j, -1)) + neg(u) * kv.second;
       }
+      F.emplace(i, f);
     }
-    // Corner Transport Upwind corrections (Algorithm 1), scattered from every cell.
+    // Corner Transport Upwind (Algorithm 1).  The jump of P across the
+    // backward j-face of cell i is a wave moving with the face velocity a.  It
+    // enters the cell on the downwind side of that face (i when a > 0, i - e_j
+    // when a < 0).  Inside that cell, half the wave times dt / h_j is carried
+    // on along each other direction l by the velocity at the cell's l-faces:
+    // out through the forward l-face where that velocity is positive, out
+    // through the backward l-face where it is negative.  The face flux changes
+    // by -a * v * dt / (2 h_j) * jump, v being the velocity at that face.
     for (const auto& kv : grid) {
       const Idx& i = kv.first;
       for (int j = 0; j < nn; ++j) {
-        const double fstar = dt / (2.0 * cfg.h[j]) * (kv.second - P(shift(i, j, -1)));
         const double a = face_vel(i, j);
+        if (a == 0.0) continue;
+        const Idx into = (a > 0.0) ? i : shift(i, j, -1);
+        const double w = dt / (2.0 * cfg.h[j]) * (kv.second - P(shift(i, j, -1)));
         for (int l = 0; l < nn; ++l) {
           if (l == j) continue;
-          const Idx ipl = shift(i, l, +1);            // forward l-face of i
-          const Idx ijm = shift(i, j, -1);            // i - e_j
-          const Idx ijmpl = shift2(i, j, -1, l, +1);  // forward l-face of i - e_j
-          F[Face{ipl, l}] -= pos(a) * pos(face_vel(ipl, l)) * fstar;
-          F[Face{i, l}] -= pos(a) * neg(face_vel(i, l)) * fstar;
-          F[Face{ijmpl, l}] -= neg(a) * pos(face_vel(ijmpl, l)) * fstar;
-          F[Face{ijm, l}] -= neg(a) * neg(face_vel(ijm, l)) * fstar;
+          const Idx ahead = shift(into, l, +1);
+          const double v_fwd = face_vel(ahead, l);  // velocity at the forward l-face of `into`
+          const double v_bwd = face_vel(into, l);   // velocity at its backward l-face
+          if (v_fwd > 0.0) add_flux(F, ahead, l, -(a * v_fwd * w));
+          if (v_bwd < 0.0) add_flux(F, into, l, -(a * v_bwd * w));
         }
       }
     }
@@ -384,7 +395,7 @@ struct Oracle {
           const double w = kv.second - P(shift(i, j, -1));
           const double wup = (u > 0.0) ? P(shift(i, j, -1)) - P(shift(i, j, -2)) : P(shift(i, j, +1)) - kv.second;
           const double au = std::fabs(u);
-          F[Face{i, j}] += 0.5 * au * (1.0 - dt * au / cfg.h[j]) * mc_limited(w, wup);
+          F.at(i)[j] += 0.5 * au * (1.0 - dt * au / cfg.h[j]) * mc_limited(w, wup);
         }
       }
     }
@@ -404,8 +415,8 @@ struct Oracle {
     const bool last = dt >= rem;
     if (last) dt = rem;
 
-    FaceMap F;
-    F.reserve(grid.size() * static_cast<size_t>(n()) * 3);
+    FluxMap F;
+    F.reserve(grid.size());
     fluxes(dt, F);
 
     Grid next;
@@ -413,11 +424,12 @@ struct Oracle {
     for (const auto& kv : grid) {
       const Idx& i = kv.first;
       double acc = kv.second;
+      const auto& own = F.at(i);
       for (int j = 0; j < n(); ++j) {
         const double dth = dt / cfg.h[j];
-        if (has(shift(i, j, -1))) acc += dth * F[Face{i, j}];
-        const Idx ip = shift(i, j, +1);
-        if (has(ip)) acc -= dth * F[Face{ip, j}];
+        if (has(shift(i, j, -1))) acc += dth * own[j];
+        const auto ahead = F.find(shift(i, j, +1));
+        if (ahead != F.end()) acc -= dth * ahead->second[j];
       }
       next.emplace(i, acc);
     }
