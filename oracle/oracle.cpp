@@ -24,6 +24,7 @@
 //      transverse propagation of it; limiter 0 gives exactly Eq. 7 + Algorithm 1;
 //   R4 grow/prune neighbour set: axis neighbours plus pairwise edge neighbours,
 //      chosen by the sign of the face velocity (downwind for grow, upwind for prune);
+//      grow_mode 2 takes every combination of those steps (the orthant, Sec. 3.3);
 //   R5 grow uses set semantics over the pre-grow grid; new cells do not grow;
 //   R6 p* = thresh_rel * max P; P == p* counts as above; zero velocity is neither
 //      up- nor downwind; with thresh_rel = 0 every non-zero cell grows (never prunes);
@@ -86,7 +87,8 @@ struct oracle_config {
   double dt_fixed;       // > 0 overrides the CFL step
   int32_t prune_every;   // prune after every prune_every-th step; 0 = never
   int32_t limiter;       // 0 none (Eq. 7 + Algorithm 1 only), 1 MC-limited high-resolution term
-  int32_t grow_mode;     // 0 directional (R4), 1 every axis and pairwise-edge neighbour
+  int32_t grow_mode;     // 0 directional (R4), 1 every axis and pairwise-edge neighbour,
+                         // 2 directional over the whole orthant (every combination of downwind steps)
 };
 
 struct oracle_stats {
@@ -201,10 +203,23 @@ struct Oracle {
     min_margin = std::min(min_margin, g);
   }
 
+  // Sum of every density, compensated (Neumaier's improvement of Kahan
+  // summation): a running sum over N cells can be off by about N * 1.1e-16
+  // relative, which at 1e7 cells exceeds the 1e-12 to which densities are
+  // compared; the compensated sum is accurate to a few units in the last place.
+  double sum_p() const {
+    double s = 0.0, c = 0.0;
+    for (const auto& kv : grid) {
+      const double v = kv.second, t = s + v;
+      c += (std::fabs(s) >= std::fabs(v)) ? (s - t) + v : (v - t) + s;
+      s = t;
+    }
+    return s + c;
+  }
+
+  // R8: scale so that V * sum P = 1.
   void normalise() {
-    double s = 0.0;
-    for (const auto& kv : grid) s += kv.second;
-    const double z = volume() * s;
+    const double z = volume() * sum_p();
     if (z > 0.0)
       for (auto& kv : grid) kv.second = kv.second / z;
   }
@@ -271,6 +286,30 @@ struct Oracle {
     return 0;
   }
 
+  // Orthant neighbour set (grow_mode 2, Sec. 3.3 and Figs. 2-3: every
+  // neighbour on the downwind side, up to 2^n - 1 of them): c plus any
+  // non-zero combination of steps, at most one per dimension, each step
+  // +e_j allowed when plus[j] and -e_j when minus[j].
+  void orthant(const Idx& c, const bool* plus, const bool* minus, std::vector<Idx>& out) const {
+    const int nn = n();
+    int step[kMaxDim] = {0, 0, 0, 0, 0, 0};
+    // Odometer over the per-dimension choices {0, +1, -1} that are allowed.
+    while (true) {
+      int j = 0;
+      while (j < nn) {
+        const int next = step[j] == 0 ? +1 : (step[j] == +1 ? -1 : 2);
+        if (next == +1 && plus[j]) { step[j] = +1; break; }
+        if ((next == +1 || next == -1) && minus[j]) { step[j] = -1; break; }
+        step[j] = 0;
+        ++j;
+      }
+      if (j == nn) return;
+      Idx o = c;
+      for (int m = 0; m < nn; ++m) o.c[m] += step[m];
+      out.push_back(o);
+    }
+  }
+
   // ---- directional grow (Sec. 3.3, R4, R5, R6) ----
   void grow_candidates(const Idx& c, std::vector<Idx>& out) const {
     const int nn = n();
@@ -282,6 +321,10 @@ struct Oracle {
         up[j] = face_vel(shift(c, j, +1), j) > 0.0;
         dn[j] = face_vel(c, j) < 0.0;
       }
+    }
+    if (cfg.grow_mode == 2) {
+      orthant(c, up, dn, out);
+      return;
     }
     for (int j = 0; j < nn; ++j) {
       if (up[j]) out.push_back(shift(c, j, +1));
@@ -471,6 +514,13 @@ struct Oracle {
         note_margin(it->second, pstar, m);
         if (it->second >= pstar) keep = true;
       };
+      if (cfg.grow_mode == 2) {
+        std::vector<Idx> ups;
+        orthant(i, up, dn, ups);
+        for (const Idx& u : ups) check(u);
+        if (!keep) dead.push_back(i);
+        continue;
+      }
       for (int j = 0; j < nn; ++j) {
         if (up[j]) check(shift(i, j, +1));
         if (dn[j]) check(shift(i, j, -1));
@@ -613,8 +663,7 @@ int64_t oracle_marginals(void* h, uint32_t dim_mask, int32_t* idx, double* val, 
 
 void oracle_get_stats(void* h, oracle_stats* s) {
   auto* o = static_cast<Oracle*>(h);
-  double sum = 0.0;
-  for (const auto& kv : o->grid) sum += kv.second;
+  const double sum = o->sum_p();
   s->t = o->t;
   s->dt_last = o->dt_last;
   s->min_margin = o->min_margin;

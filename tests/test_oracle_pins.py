@@ -475,3 +475,117 @@ def test_marginals_brute_force_and_gaussian(oracle_mod):
     sub = S.linear_config(2, [0.0] * 6, h=0.25, mean=[1.0, 0.5])
     m, c = _ref.grid_moments(sub, mi, mv)
     assert np.allclose(m, [1.0, 0.5], atol=1e-6) and np.allclose(c, np.diag([0.5, 0.6]), atol=1e-5)
+
+
+# ---------------------------------------------------------------------------
+# Grow and prune neighbour sets at n = 3 and n = 6, pairwise (grow_mode 0) and
+# orthant (grow_mode 2), by brute force over all 3^n - 1 offsets with the
+# velocity signs of the independent numpy drift (tests/_ref.py).
+# ---------------------------------------------------------------------------
+
+def _face_signs(cfg, idx):
+    """Per cell and dimension: forward-face velocity > 0 / < 0, backward-face velocity < 0 / > 0."""
+    n = cfg["n"]
+    fwd_pos = np.zeros((len(idx), n), bool)
+    fwd_neg = np.zeros((len(idx), n), bool)
+    bwd_neg = np.zeros((len(idx), n), bool)
+    bwd_pos = np.zeros((len(idx), n), bool)
+    for j in range(n):
+        ub = _ref.face_velocity(cfg, idx, j)
+        uf = _ref.face_velocity(cfg, idx + np.eye(n, dtype=idx.dtype)[j], j)
+        fwd_pos[:, j], fwd_neg[:, j] = uf > 0, uf < 0
+        bwd_neg[:, j], bwd_pos[:, j] = ub < 0, ub > 0
+    return fwd_pos, fwd_neg, bwd_neg, bwd_pos
+
+
+def _offset_ok(d, plus, minus, max_nonzero):
+    nz = np.count_nonzero(d)
+    if not 1 <= nz <= max_nonzero:
+        return False
+    return all((s == 0) or (s == 1 and plus[j]) or (s == -1 and minus[j]) for j, s in enumerate(d))
+
+
+GROW_PRUNE_CASES = [
+    ("l63", 0), ("l63", 2), ("l96", 0), ("l96", 2),
+]
+
+
+def _set_case(name, mode):
+    if name == "l63":
+        return S.with_(S.l63_small(), thresh_rel=1e-2, grow_mode=mode)
+    return S.with_(S.l96_6d(h=0.6, thresh_rel=1e-2), grow_mode=mode)
+
+
+@pytest.mark.parametrize("name,mode", GROW_PRUNE_CASES)
+def test_grow_set_brute_force_all_offsets(oracle_mod, name, mode):
+    """Grow adds exactly the offsets whose every step is downwind: pairwise
+    (at most two steps, R4) or the whole orthant (any number, Sec. 3.3)."""
+    cfg = _set_case(name, mode)
+    n = cfg["n"]
+    o = oracle_mod.Oracle(cfg).init_gaussian()
+    idx, p = o.export()
+    pstar = cfg["thresh_rel"] * p.max()
+    up, _, dn, _ = _face_signs(cfg, idx)
+    limit = 2 if mode == 0 else n
+    offsets = [np.array(d) for d in itertools.product([-1, 0, 1], repeat=n) if any(d)]
+    want = set(map(tuple, idx))
+    for k in np.flatnonzero(p >= pstar):
+        for d in offsets:
+            if _offset_ok(d, up[k], dn[k], limit):
+                want.add(tuple(idx[k] + d))
+    o.grow()
+    gi, _ = o.export()
+    assert set(map(tuple, gi)) == want
+    assert len(want) > len(idx)
+
+
+@pytest.mark.parametrize("name,mode", GROW_PRUNE_CASES)
+def test_prune_set_brute_force_all_offsets(oracle_mod, name, mode):
+    """A cell below p* survives exactly when a neighbour at an upwind offset
+    (every step upwind; at most two steps, or any number in the orthant
+    mode) holds at least p*."""
+    cfg = _set_case(name, mode)
+    n = cfg["n"]
+    o = oracle_mod.Oracle(cfg).init_gaussian()
+    o.grow()
+    o.step(10.0, 3)
+    idx, p = o.export()
+    cells = {tuple(i): v for i, v in zip(idx, p)}
+    pstar = cfg["thresh_rel"] * p.max()
+    _, fneg, _, bpos = _face_signs(cfg, idx)
+    limit = 2 if mode == 0 else n
+    offsets = [np.array(d) for d in itertools.product([-1, 0, 1], repeat=n) if any(d)]
+    keep = set()
+    for k, (c, v) in enumerate(zip(idx, p)):
+        if v >= pstar:
+            keep.add(tuple(c))
+            continue
+        for d in offsets:
+            u = tuple(c + d)
+            if u in cells and cells[u] >= pstar and _offset_ok(d, fneg[k], bpos[k], limit):
+                keep.add(tuple(c))
+                break
+    o.prune()
+    gi, _ = o.export()
+    assert set(map(tuple, gi)) == keep
+    assert len(keep) < len(idx)
+
+
+def test_orthant_grid_contains_pairwise_grid(oracle_mod):
+    """The orthant set contains the pairwise one, so with the same start the
+    orthant grow keeps a superset of cells, and for n = 2 the two coincide."""
+    for name in ("l63", "l96"):
+        a = oracle_mod.Oracle(_set_case(name, 0)).init_gaussian()
+        b = oracle_mod.Oracle(_set_case(name, 2)).init_gaussian()
+        a.grow()
+        b.grow()
+        sa, sb = set(map(tuple, a.export()[0])), set(map(tuple, b.export()[0]))
+        assert sa <= sb and (name == "l63" or len(sb) > len(sa))
+    ab = S.random_linear(2, seed=3, scale=0.8)
+    c0 = S.linear_config(2, ab, h=0.4, thresh_rel=1e-3, cov=0.5 * np.eye(2), cfl=0.8)
+    runs = []
+    for mode in (0, 2):
+        o = oracle_mod.Oracle(S.with_(c0, grow_mode=mode)).init_gaussian()
+        o.step(0.5)
+        runs.append(o.export())
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
