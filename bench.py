@@ -39,6 +39,21 @@ def flux_a_bytes_per_brick(n, real_size):
     return 64 * real_size + 8 + 8 + 4 * 2 * n + n * 32 * real_size
 
 
+def alg_bytes_per_cell_update(n, real_size):
+    """Algorithmic bytes of one cell-update of the flux + update pass (per cell,
+    cell state read once and written once, connectivity stored per cell): the
+    packed key (8, for the drift), P read and P' written (2 s) and 2n four-byte
+    axis-neighbour indices.  72 B in 6-D FP64, 64 B in 6-D FP32, 48 B in 3-D
+    FP64."""
+    return 8 + 2 * real_size + 4 * 2 * n
+
+
+# Whole-step bytes per cell-update of the 6-D FP64 method (flux + update, the
+# grow check and the prune amortised over 20 steps), the model the end-to-end
+# figure is read against.
+WHOLE_STEP_BYTES_6D_FP64 = 160.0
+
+
 def fused_bytes_per_brick(n, real_size):
     """Lower bound for any one-pass form of the whole flux + update: density
     row in, updated row out, key, mask and links."""
@@ -173,6 +188,20 @@ def run_job(G, cfg, max_cells, profile, probe=False):
     return st, prof
 
 
+def host_cpu():
+    """The host's CPU model and logical core count (the oracle uses one thread)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count()}
+
+
 def cpu_baseline(budget_s):
     """The oracle, single-threaded, on the downsampled L96 6D grid (h = 0.5, thr
     1e-5): as many whole steps as fit in the time budget."""
@@ -186,9 +215,32 @@ def cpu_baseline(budget_s):
         o.step(cfg["t_end"], 1)
     dt = time.perf_counter() - t0
     st = o.stats()
+    cpu = host_cpu()
     return {"value": st["cell_updates"] / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"L96 6D h=0.5 thr=1e-5 ({o.count()} cells), first {st['steps']} steps, "
-                      f"{dt:.1f} s single-threaded"}
+                      f"{dt:.1f} s single-threaded", "host_cpu": cpu["model"], "host_nproc": cpu["nproc"]}
+
+
+def cpu_baseline_full(c3_steps):
+    """The oracle on the Lorenz '63 workload in full and on the first steps of
+    the full Lorenz '96 6D benchmark grid (1.1e7 initial cells), single-threaded:
+    cell-updates per second of the step loop (initialisation timed apart)."""
+    import oracle
+    from paper_2508_13986_amd import scenarios as S
+
+    out = {"kind": "oracle", "cores": 1, **host_cpu()}
+    for name, cfg, steps in (("l63_small", S.l63_small(), 0), ("l96_6d", S.l96_6d(), c3_steps)):
+        t0 = time.perf_counter()
+        o = oracle.Oracle(cfg).init_gaussian()
+        t1 = time.perf_counter()
+        o.step(cfg["t_end"], steps)
+        t2 = time.perf_counter()
+        st = o.stats()
+        out[name] = {"init_s": t1 - t0, "steps": st["steps"], "step_s": t2 - t1, "cell_updates": st["cell_updates"],
+                     "cell_updates_per_s": st["cell_updates"] / (t2 - t1), "cells_final": st["cells"],
+                     "span": "whole horizon t in [0, 0.5]" if steps == 0 else f"first {steps} steps (per-cell-update rate)"}
+        print(name, json.dumps(out[name]), flush=True)
+    return out
 
 
 def main():
@@ -205,6 +257,9 @@ def main():
     ap.add_argument("--pool-gib", type=float, default=160.0, help="serving: arena of the pool")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-baseline-full", type=int, default=0, metavar="STEPS",
+                    help="only time the oracle: Lorenz-63 workload in full and the first STEPS steps of the full "
+                         "Lorenz-96 grid; prints one JSON line")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run one plain device copy of this many bytes (for counter calibration)")
     args = ap.parse_args()
@@ -213,6 +268,10 @@ def main():
         print("bench.py runs on one GPU only: there is no multi-GPU path (requests or Morton ranges would be sharded; not implemented)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.cpu_baseline_full:
+        print(json.dumps(cpu_baseline_full(args.cpu_baseline_full)), flush=True)
+        return
 
     if args.workload == "serving":
         serving_bench(args)
@@ -266,11 +325,13 @@ def main():
     avg_a = fa_ms / 1e3 / max(fa_n, 1)
     bytes_b = flux_b_bytes_per_brick(n, real_size) * bricks_per_launch
     bytes_a = flux_a_bytes_per_brick(n, real_size) * bricks_per_launch
-    achieved = bytes_b / avg_b / 1e9
     rec = pmc_record(args.workload)
     traffic = measured_traffic(rec, bricks_per_launch)
     valu_busy = rec.get("derived", {}).get("valu_busy_pct") if rec else None
     cells_per_step = totals["cell_updates"] / max(totals["steps"], 1)
+    # The method's bytes: per cell-update, for the cells one launch updates.
+    alg_per_launch = alg_bytes_per_cell_update(n, real_size) * cells_per_step
+    achieved = alg_per_launch / avg_b / 1e9
     line = {
         "metric": "CTU cell-updates/s (Lorenz-96 6D)",
         "value": value,
@@ -306,17 +367,32 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
             "traffic": traffic,
+            "basis": f"{alg_bytes_per_cell_update(n, real_size)} B per cell-update x cells per launch",
             "valu_busy_pct": valu_busy,
             "avg_launch_us": avg_b * 1e6,
-            "algorithmic_bytes_per_launch": bytes_b,
+            "algorithmic_bytes_per_launch": alg_per_launch,
+        },
+        # The whole flux + update step (both passes) against the same bytes.
+        "flux_step_roofline": {
+            "achieved": alg_per_launch / (avg_a + avg_b) / 1e9,
+            "frac": alg_per_launch / (avg_a + avg_b) / 1e9 / HBM_PEAK_GBPS,
+            "ms_per_step": (avg_a + avg_b) * 1e3,
+        },
+        "end_to_end_roofline": {
+            "achieved": value * WHOLE_STEP_BYTES_6D_FP64 / 1e9 if (n == 6 and real_size == 8) else None,
+            "frac": value * WHOLE_STEP_BYTES_6D_FP64 / 1e9 / HBM_PEAK_GBPS if (n == 6 and real_size == 8) else None,
+            "basis": f"{WHOLE_STEP_BYTES_6D_FP64:.0f} B per 6-D FP64 cell-update (flux, grow check, prune every 20)",
         },
         "phases_ms_per_job": {k: v[0] / args.steps for k, v in prof_sum.items()},
         "flux_passes_cell_updates_per_s": cells_per_step / (avg_a + avg_b),
-        "flux_a_gbps": bytes_a / avg_a / 1e9,
-        "flux_step_vs_fused_bound": {
-            "bytes_per_brick": fused_bytes_per_brick(n, real_size),
-            "gbps": fused_bytes_per_brick(n, real_size) * bricks_per_launch / (avg_a + avg_b) / 1e9,
-            "frac": fused_bytes_per_brick(n, real_size) * bricks_per_launch / (avg_a + avg_b) / 1e9 / HBM_PEAK_GBPS,
+        # Per-kernel diagnostics on the brick-slot basis (every lane of every
+        # swept brick, plus the corrected-state face layers of the two-pass form).
+        "slot_basis": {
+            "flux_b_bytes_per_brick": flux_b_bytes_per_brick(n, real_size),
+            "flux_b_gbps": bytes_b / avg_b / 1e9,
+            "flux_a_gbps": bytes_a / avg_a / 1e9,
+            "fused_bound_bytes_per_brick": fused_bytes_per_brick(n, real_size),
+            "fused_bound_frac": fused_bytes_per_brick(n, real_size) * bricks_per_launch / (avg_a + avg_b) / 1e9 / HBM_PEAK_GBPS,
         },
     }
     if real_size == 4 and not args.no_accuracy:

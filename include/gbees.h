@@ -25,8 +25,16 @@
  *    config); index arrays are row-major [count][n] int32.
  *  - Densities are cell averages normalised so that prod(h) * sum P = 1.
  *  - Exported cells are sorted lexicographically by index.
- *  - After GBEES_E_CAPACITY or GBEES_E_RANGE the context is unusable except
- *    for gbees_get_stats and gbees_destroy (every other call returns the error).
+ *  - GBEES_E_CAPACITY or GBEES_E_RANGE from gbees_step (a grow that needed
+ *    more bricks or hashtable slots than max_cells provides, or a cell index
+ *    outside the packable range) leaves the grid as it was at the start of the
+ *    step that failed: time, step count, cells and densities.  The context
+ *    stays usable: gbees_export it, or move it into a larger arena with
+ *    gbees_resize and step on.  Stepping again without more capacity fails
+ *    at the same step.
+ *  - After any other error the context is unusable except for
+ *    gbees_get_stats and gbees_destroy (every other call returns
+ *    GBEES_E_STATE).
  *  - Not thread-safe per context; distinct contexts are independent.
  */
 #ifndef GBEES_H
@@ -68,7 +76,10 @@ typedef struct {
   double dt_fixed;     /* > 0 replaces the CFL step (tests) */
   int32_t prune_every; /* prune after every prune_every-th step; 0 = never */
   int32_t limiter;     /* 0: Eq. 7 + Algorithm 1 only; 1: plus the MC-limited high-resolution term */
-  int32_t grow_mode;   /* 0: downwind axis and pairwise-edge neighbours; 1: every one of them */
+  int32_t grow_mode;   /* 0: downwind axis and pairwise-edge neighbours; 1: every one of them;
+                          2: every combination of downwind steps, one per dimension (the orthant,
+                          up to 2^n - 1 cells, Sec. 3.3); prune mirrors the choice upwind.
+                          The serving pool takes modes 0 and 1 only. */
   int32_t precision;   /* 0: FP64 densities; 1: FP32 densities and fluxes, FP64 reductions */
   int64_t max_cells;   /* capacity in cell slots (cells are stored in bricks of 64) */
   double hash_load;    /* hashtable load bound (Sec. 4.2), 0 => 0.5 */
@@ -88,6 +99,8 @@ typedef struct {
   int64_t prunes;        /* prune passes run */
   int64_t grow_bricks;   /* bricks the grow pass expanded (cells newly above threshold since the last prune) */
   int64_t inserted;      /* cells created by grow */
+  int64_t deferred;      /* grow inserts whose brick another wave was still creating, finished by the fix-up pass */
+  double mass_pruned;    /* sum over prunes of the fraction of the mass present that each prune removed */
 } gbees_stats;
 
 /* Device bytes the arena must hold for cfg (0 if cfg is invalid). */
@@ -127,6 +140,15 @@ int gbees_marginals(gbees_ctx* ctx, uint32_t dim_mask, int64_t capacity, int32_t
 /* Copy the grid out: idx[count][n], P[count] sorted by index, and the time.
  * GBEES_E_BUFFER (with *count set) if capacity < count.  t may be NULL. */
 int gbees_export(gbees_ctx* ctx, int64_t capacity, int32_t* idx, double* P, int64_t* count, double* t);
+
+/* Move the grid into a new arena of at least gbees_arena_bytes(cfg with
+ * max_cells) bytes, which must not overlap the current one, and keep
+ * stepping there with capacity max_cells (Sec. 4.1: the capacity is fixed per
+ * arena, so a grid that outgrows it moves).  Cells, densities, time, step
+ * count and statistics carry over; the old arena is free for the caller once
+ * this returns.  GBEES_E_CAPACITY if max_cells cannot hold the current
+ * bricks.  Device-to-device copies on the context's stream; no allocation. */
+int gbees_resize(gbees_ctx* ctx, int64_t max_cells, void* arena, size_t arena_bytes);
 
 /* Current statistics (synchronises the stream). */
 int gbees_get_stats(gbees_ctx* ctx, gbees_stats* out);
@@ -181,19 +203,22 @@ typedef struct {
   int64_t arena_bytes; /* its footprint */
   int64_t cells;       /* cells in the result */
   gbees_stats stats;   /* statistics of the finished propagation */
+  int64_t resizes;     /* times the request's grid outgrew its capacity and moved into a larger slice */
 } gbees_req_info;
 
 /* arena: device buffer of arena_bytes owned by the caller for the pool's
  * life; max_active (1..256): requests running at once.  All pool calls may come
- * from any thread; gbees_pool_result and gbees_pool_release of one request must
- * not overlap. */
+ * from any thread.  Concurrent gbees_pool_result calls for one request share
+ * its one copy; gbees_pool_release during such a copy returns GBEES_E_STATE. */
 int gbees_pool_create(void* arena, size_t arena_bytes, int32_t max_active, gbees_pool** out);
 
 /* Queue a request: initialise from the Gaussian of cfg (as gbees_init_gaussian),
  * step to each measurement time in order, correct (as gbees_correct), step to
  * t_end.  Requires cfg->thresh_rel > 0.  meas is copied.  *req receives its id.
  * GBEES_E_CAPACITY if its footprint exceeds the whole arena.  A request whose
- * grid outgrows cfg->max_cells ends with status GBEES_E_CAPACITY. */
+ * grid outgrows its capacity continues from the step that failed in a slice
+ * of four (else two) times the capacity (gbees_resize); only when no such
+ * slice is free does it end with status GBEES_E_CAPACITY. */
 int gbees_pool_submit(gbees_pool* pool, const gbees_config* cfg, double t_end, const gbees_meas* meas,
                       int32_t n_meas, int64_t* req);
 
@@ -210,6 +235,10 @@ int gbees_pool_info(gbees_pool* pool, int64_t req, gbees_req_info* out);
  * slice.  GBEES_E_STATE while it runs; its error code if it failed;
  * GBEES_E_BUFFER (with *count set) if capacity < count. */
 int gbees_pool_result(gbees_pool* pool, int64_t req, int64_t capacity, int32_t* idx, double* P, int64_t* count);
+
+/* Requests of one kind that one driver steps with shared launches (1..64,
+ * default 4); applies to groups formed after the call. */
+int gbees_pool_group_size(gbees_pool* pool, int32_t k);
 
 /* Forget a finished or failed request, freeing its arena slice if it still
  * holds one.  Release every finished request: its slice is not reused before. */

@@ -54,7 +54,7 @@ bool valid_config(const gbees_config& c) {
     if (!(c.h[j] > 0.0) || !std::isfinite(c.h[j]) || !std::isfinite(c.mean[j])) return false;
   if (!(c.thresh_rel >= 0.0 && c.thresh_rel < 1.0)) return false;
   if (!(c.dt_fixed > 0.0) && !(c.cfl > 0.0 && c.cfl <= 1.0)) return false;
-  if (c.prune_every < 0 || (c.limiter != 0 && c.limiter != 1) || (c.grow_mode != 0 && c.grow_mode != 1)) return false;
+  if (c.prune_every < 0 || (c.limiter != 0 && c.limiter != 1) || c.grow_mode < 0 || c.grow_mode > 2) return false;
   if (c.precision != 0 && c.precision != 1) return false;
   if (c.max_cells < gbees::kLanes) return false;
   if (c.max_cells / gbees::kLanes > 0xF0000000ll) return false;
@@ -222,12 +222,24 @@ struct gbees_ctx {
     prof.harvest();
     return absorb();
   }
-  // Host bookkeeping after a fresh copy of the scalar block landed in hsb.
+  // Host bookkeeping after a fresh copy of the scalar block landed in hsb.  A
+  // grow that ran out of capacity or coordinate range is rolled back to the
+  // start of its step: the error is returned and the context stays usable.
   int absorb() {
     nb_est = std::max<uint32_t>(std::min<uint32_t>(hsb.nb, L.cap_b), 64);
     host_steps = static_cast<int64_t>(hsb.steps);
-    if (hsb.status != 0) return fail(hsb.status == gbees::kErrRange ? GBEES_E_RANGE : GBEES_E_CAPACITY);
-    return GBEES_OK;
+    if (hsb.status == 0) return GBEES_OK;
+    const int code = hsb.status == gbees::kErrRange ? GBEES_E_RANGE : GBEES_E_CAPACITY;
+    if (hsb.status != gbees::kErrCapacity && hsb.status != gbees::kErrRange) return fail(code);
+    kt->rollback(dev, stream, G());
+    if (hipMemcpyAsync(&hsb, base + L.sb, sizeof(Scalars), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+      return fail(GBEES_E_DEVICE);
+    prof.harvest();
+    nb_est = std::max<uint32_t>(std::min<uint32_t>(hsb.nb, L.cap_b), 64);
+    host_steps = static_cast<int64_t>(hsb.steps);
+    if (hsb.status != 0) return fail(code);
+    return code;
   }
   // Enqueue up to K steps toward t_stop (steps past it are no-ops on the
   // device), with a prune or renormalisation after every prune_every-th step.
@@ -272,6 +284,13 @@ bool upload_dev(gbees_ctx* c) {
          hipSuccess;
 }
 
+// Delete a context whose stream may still hold work of new_ctx (clears and
+// the upload of its Dev block, which reads the context itself).
+void discard(gbees_ctx* c) {
+  hipStreamSynchronize(c->stream);
+  delete c;
+}
+
 gbees_ctx* new_ctx(const gbees_config* cfg, void* arena, size_t bytes, void* stream, int* err) {
   *err = GBEES_E_ARG;
   if (!cfg || !arena) return nullptr;
@@ -293,12 +312,14 @@ gbees_ctx* new_ctx(const gbees_config* cfg, void* arena, size_t bytes, void* str
   }
   std::memset(&c->hsb, 0, sizeof(c->hsb));
   if (hipMemsetAsync(c->base, 0, L.zero_end, c->stream) != hipSuccess ||
-      hipMemsetAsync(c->base + L.zero_end, 0xFF, L.ff_end - L.zero_end, c->stream) != hipSuccess ||
-      !upload_dev(c)) {
-    delete c;
+      hipMemsetAsync(c->base + L.zero_end, 0xFF, L.ff_end - L.zero_end, c->stream) != hipSuccess) {
+    discard(c);
     *err = GBEES_E_DEVICE;
     return nullptr;
   }
+  // The Dev block is uploaded by the caller once it is complete: the copy
+  // reads the host block when it executes, so the block must not change
+  // until the stream has passed it.
   *err = GBEES_OK;
   return c;
 }
@@ -309,13 +330,6 @@ void with_dev(gbees_ctx* c, F f) {
     f(c->d32);
   else
     f(c->d64);
-}
-
-// Delete a context whose stream may still hold work of new_ctx (clears and
-// the upload of its Dev block, which reads the context itself).
-void discard(gbees_ctx* c) {
-  hipStreamSynchronize(c->stream);
-  delete c;
 }
 
 int check_ctx(gbees_ctx* c) {
@@ -488,6 +502,10 @@ int gbees_init_cells(const gbees_config* cfg, const int32_t* idx, const double* 
   int err;
   gbees_ctx* c = new_ctx(cfg, arena, arena_bytes, hip_stream, &err);
   if (!c) return err;
+  if (!upload_dev(c)) {
+    discard(c);
+    return GBEES_E_DEVICE;
+  }
   const int n = cfg->n;
   // Group cells into bricks, bricks ordered by packed key.
   std::unordered_map<u64, uint32_t> where;
@@ -541,6 +559,7 @@ int gbees_init_cells(const gbees_config* cfg, const int32_t* idx, const double* 
   if (!keys.empty()) {
     okc = hipMemcpyAsync(c->base + c->L.key, keys.data(), keys.size() * 8, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
           hipMemcpyAsync(c->base + c->L.mask, mask.data(), mask.size() * 8, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+          hipMemcpyAsync(c->base + c->L.abv, mask.data(), mask.size() * 8, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
           hipMemcpyAsync(c->base + c->L.P0, pbuf.data(), pbuf.size(), hipMemcpyHostToDevice, c->stream) == hipSuccess;
   }
   okc = okc && hipMemcpyAsync(c->base + c->L.sb, &s0, sizeof(s0), hipMemcpyHostToDevice, c->stream) == hipSuccess;
@@ -686,8 +705,58 @@ int gbees_get_stats(gbees_ctx* c, gbees_stats* out) {
     out->prunes = static_cast<int64_t>(c->hsb.prunes);
     out->grow_bricks = static_cast<int64_t>(c->hsb.grow_bricks);
     out->inserted = static_cast<int64_t>(c->hsb.inserted);
+    out->deferred = static_cast<int64_t>(c->hsb.deferred);
+    out->mass_pruned = c->hsb.pruned;
   }
   return c->status;
+}
+
+int gbees_resize(gbees_ctx* c, int64_t max_cells, void* arena, size_t arena_bytes) {
+  int rc = check_ctx(c);
+  if (rc != GBEES_OK) return rc;
+  if (!arena) return GBEES_E_ARG;
+  gbees_config cfg = c->cfg;
+  cfg.max_cells = max_cells;
+  Layout L;
+  if (!make_layout(cfg, &L) || arena_bytes < L.total) return GBEES_E_ARG;
+  char* nb_base = static_cast<char*>(arena);
+  if (nb_base < c->base + c->L.total && c->base < nb_base + L.total) return GBEES_E_ARG;  // overlap
+  rc = c->sync_read();
+  if (rc != GBEES_OK) return rc;
+  const uint32_t nb = std::min<uint32_t>(c->hsb.nb, c->L.cap_b);
+  if (nb > L.cap_b) return GBEES_E_CAPACITY;
+  hipStream_t s = c->stream;
+  const size_t rows = static_cast<size_t>(nb) * gbees::kLanes * c->L.real_size;
+  Scalars sb = c->hsb;
+  sb.cur = 0;
+  bool ok = hipMemsetAsync(nb_base, 0, L.zero_end, s) == hipSuccess &&
+            hipMemsetAsync(nb_base + L.zero_end, 0xFF, L.ff_end - L.zero_end, s) == hipSuccess;
+  if (ok && nb > 0)
+    ok = hipMemcpyAsync(nb_base + L.key, c->base + c->L.key, nb * 8, hipMemcpyDeviceToDevice, s) == hipSuccess &&
+         hipMemcpyAsync(nb_base + L.mask, c->base + c->L.mask, nb * 8, hipMemcpyDeviceToDevice, s) == hipSuccess &&
+         hipMemcpyAsync(nb_base + L.abv, c->base + c->L.mask, nb * 8, hipMemcpyDeviceToDevice, s) == hipSuccess &&
+         hipMemcpyAsync(nb_base + L.done, c->base + c->L.done, nb * 8, hipMemcpyDeviceToDevice, s) == hipSuccess &&
+         hipMemcpyAsync(nb_base + L.P0, c->base + (c->hsb.cur ? c->L.P1 : c->L.P0), rows, hipMemcpyDeviceToDevice,
+                        s) == hipSuccess;
+  ok = ok && hipMemcpyAsync(nb_base + L.sb, &sb, sizeof(sb), hipMemcpyHostToDevice, s) == hipSuccess;
+  if (!ok) return c->fail(GBEES_E_DEVICE);
+  // The context now describes the new arena; the initial-condition fields of
+  // its Dev block carry over.
+  with_dev(c, [&](auto& d) {
+    auto keep = d;
+    fill_dev(d, cfg, L, nb_base);
+    std::memcpy(d.sinv, keep.sinv, sizeof(d.sinv));
+    d.bound = keep.bound;
+    std::memcpy(d.box_lo, keep.box_lo, sizeof(d.box_lo));
+    std::memcpy(d.box_n, keep.box_n, sizeof(d.box_n));
+    d.box_count = keep.box_count;
+  });
+  c->cfg = cfg;
+  c->L = L;
+  c->base = nb_base;
+  if (!upload_dev(c)) return c->fail(GBEES_E_DEVICE);
+  c->kt->relink(c->dev, s, c->G());
+  return c->sync_read();  // also keeps sb alive until its copy finished
 }
 
 int gbees_probe_stats(gbees_ctx* c, int64_t n_miss, double* mean_hit, double* mean_miss, double* load) {
@@ -816,7 +885,9 @@ struct PoolRequest {
   double t_submit = 0.0, t_admit = 0.0, t_done = 0.0;
   gbees_stats stats{};
   std::vector<CellRow> rows;
+  bool exporting = false;  // a gbees_pool_result call is copying the grid out
   bool exported = false;
+  int64_t resizes = 0;     // moves into a larger arena slice after the grid outgrew its capacity
 };
 
 // A request's place in its group's run: the context, the next measurement
@@ -850,13 +921,14 @@ struct PoolGroup {
 struct gbees_pool {
   // Requests per driver: enough to share launches, few enough that several
   // drivers of one kind overlap on the device while one of them waits for its
-  // batch, reads back scalars or corrects.
-  static constexpr int kPerDriver = 4;
+  // batch, reads back scalars or corrects.  (gbees_pool_group_size sets it.)
+  int per_driver = 4;
   char* base = nullptr;
   size_t total = 0;
   SliceAllocator slices{0};
   std::mutex mu;
   std::condition_variable work_cv;
+  std::condition_variable export_cv;  // a result copy finished
   std::deque<int64_t> pending;  // waiting for a slot and a slice
   std::unordered_map<int64_t, PoolRequest> reqs;
   std::vector<std::unique_ptr<PoolGroup>> groups;
@@ -869,12 +941,12 @@ struct gbees_pool {
   double now() const { return std::chrono::duration<double>(PoolClock::now() - t0).count(); }
 
   // The group of the request's kind with the fewest members, or a new one if
-  // each has kPerDriver.  (Caller holds mu.)
+  // each has per_driver.  (Caller holds mu.)
   PoolGroup* group_for(const gbees_config& cfg) {
     const int model = effective_model(cfg), prec = cfg.precision == 1 ? 1 : 0;
     PoolGroup* best = nullptr;
     for (auto& g : groups)
-      if (g->model == model && g->n == cfg.n && g->precision == prec && g->members < kPerDriver &&
+      if (g->model == model && g->n == cfg.n && g->precision == prec && g->members < per_driver &&
           (!best || g->members < best->members))
         best = g.get();
     if (best) return best;
@@ -912,6 +984,37 @@ struct gbees_pool {
     if (rc != GBEES_OK) free_request(*x.r);
     --busy;
     --g.members;
+  }
+
+  // A runner whose grid outgrew its capacity (its last step was rolled back):
+  // move it into a slice four, else two, times as large and keep it running.
+  // False if no slice that large is free now.
+  bool enlarge(Runner& x) {
+    PoolRequest& r = *x.r;
+    for (int64_t factor : {4, 2}) {
+      gbees_config cfg = r.cfg;
+      cfg.max_cells = r.cfg.max_cells * factor;
+      const size_t bytes = gbees_arena_bytes(&cfg);
+      if (bytes == 0) continue;
+      size_t off = 0;
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        if (!slices.take(bytes, &off)) continue;
+      }
+      const int rc = gbees_resize(x.c, cfg.max_cells, base + off, bytes);
+      std::lock_guard<std::mutex> lk(mu);
+      if (rc != GBEES_OK) {
+        slices.give(off, bytes);
+        return false;
+      }
+      slices.give(r.off, r.bytes);
+      r.off = off;
+      r.bytes = bytes;
+      r.cfg.max_cells = cfg.max_cells;
+      ++r.resizes;
+      return true;
+    }
+    return false;
   }
 
   // Measurements due now (t reached), then the end: corrections and exits.
@@ -1007,6 +1110,10 @@ struct gbees_pool {
       std::vector<Runner> keep;
       for (auto& x : run) {
         const int rx = rc != GBEES_OK ? rc : x.c->absorb();
+        if (rx == GBEES_E_CAPACITY && x.c->status == GBEES_OK && enlarge(x)) {
+          keep.push_back(x);
+          continue;
+        }
         if (rx != GBEES_OK) {
           leave(g, x, rx);
           continue;
@@ -1056,7 +1163,7 @@ int gbees_pool_submit(gbees_pool* p, const gbees_config* cfg, double t_end, cons
                       int64_t* req) {
   if (!p || !cfg || !req || nm < 0 || (nm > 0 && !meas) || !std::isfinite(t_end) || t_end < 0.0) return GBEES_E_ARG;
   const size_t bytes = gbees_arena_bytes(cfg);
-  if (bytes == 0 || !(cfg->thresh_rel > 0.0)) return GBEES_E_ARG;
+  if (bytes == 0 || !(cfg->thresh_rel > 0.0) || cfg->grow_mode == 2) return GBEES_E_ARG;
   if (align_up(bytes) > p->total) return GBEES_E_CAPACITY;  // could never be admitted
   PoolRequest r;
   r.cfg = *cfg;
@@ -1131,6 +1238,7 @@ int gbees_pool_info(gbees_pool* p, int64_t req, gbees_req_info* out) {
   out->cells = r.status == 2 ? r.stats.cells : 0;
   std::memset(&out->stats, 0, sizeof(out->stats));
   if (r.status == 2) out->stats = r.stats;
+  out->resizes = r.resizes;
   return GBEES_OK;
 }
 
@@ -1142,15 +1250,20 @@ int gbees_pool_result(gbees_pool* p, int64_t req, int64_t capacity, int32_t* idx
   PoolRequest& r = it->second;
   if (r.status < 0) return r.status;
   if (r.status != 2) return GBEES_E_STATE;
+  // A concurrent call for the same request waits for the first one's copy.
+  p->export_cv.wait(lk, [&] { return !r.exporting; });
   if (!r.exported) {
     // First call: copy the grid out (outside the lock: the drivers keep running)
-    // and free the device side.  The caller owns the finished request, so no
-    // other thread touches its context meanwhile.
+    // and free the device side.  The exporting flag keeps every other call
+    // (result or release) off the context meanwhile.
     gbees_ctx* c = r.ctx;
+    r.exporting = true;
     lk.unlock();
     std::vector<CellRow> rows;
     const int rc = host_cells(c, &rows);
     lk.lock();
+    r.exporting = false;
+    p->export_cv.notify_all();
     if (rc != GBEES_OK) return rc;
     r.rows = std::move(rows);
     r.exported = true;
@@ -1173,9 +1286,16 @@ int gbees_pool_release(gbees_pool* p, int64_t req) {
   auto it = p->reqs.find(req);
   if (it == p->reqs.end()) return GBEES_E_ARG;
   PoolRequest& r = it->second;
-  if (r.status == 0 || r.status == 1) return GBEES_E_STATE;
+  if (r.status == 0 || r.status == 1 || r.exporting) return GBEES_E_STATE;
   p->free_request(r);
   p->reqs.erase(it);
+  return GBEES_OK;
+}
+
+int gbees_pool_group_size(gbees_pool* p, int32_t k) {
+  if (!p || k < 1 || k > gbees::kMultiMax) return GBEES_E_ARG;
+  std::lock_guard<std::mutex> lk(p->mu);
+  p->per_driver = k;
   return GBEES_OK;
 }
 

@@ -159,6 +159,10 @@ struct Scalars {
   int32_t status;
   uint32_t overflow;      // scratch-table overflow of the last marginal call
   u64 steps, cell_updates, brick_updates, cells, prunes, inserted, grow_bricks;
+  u64 deferred;           // grow records finished by the fix-up pass, over all steps
+  u64 smax_begin;         // smax_bits at the start of the current step (restored on a failed grow)
+  double sum_pre;         // sum P when the current prune began
+  double pruned;          // sum over prunes of the fraction of the mass each one removed
 };
 
 // ---------------------------------------------------------------------------
@@ -185,7 +189,8 @@ struct Dev {
   u64* key;            // [cap_b + 1]
   u64* mask;           // [cap_b + 1]
   u64* done;           // [cap_b + 1] cells whose grow candidates are known to be present
-  u64* abv;            // [cap_b + 1] above-threshold lanes (prune)
+  u64* abv;            // [cap_b + 1] above-threshold lanes inside a prune; between prunes, the
+                       // occupancy masks at the start of the next step (restored on a failed grow)
   uint32_t* nbr;       // [2n][cap_b + 1]; entry 2j is the -e_j neighbour, 2j+1 the +e_j neighbour
   Real* P0;            // [(cap_b + 1) * 64]
   Real* P1;            // [(cap_b + 1) * 64]

@@ -88,8 +88,14 @@ struct KernelTable {
   // One time step of every grid in m (each gated on its own device state), as
   // `step` would take it alone with its own workgroup count.
   void (*step_multi)(const MultiGrids& m, hipStream_t s);
+  // After a grow that failed for lack of capacity or coordinate range: the
+  // grid as it was when that step began, with a clear status.
+  void (*rollback)(const void* dev, hipStream_t s, uint32_t G);
+  // Hashtable and axis links rebuilt from the brick keys and masks.
+  void (*relink)(const void* dev, hipStream_t s, uint32_t G);
 };
 
 const KernelTable* kernel_table(int model, int n, int precision);
+
 
 }  // namespace gbees

@@ -207,7 +207,9 @@ enum ScalarOp : int {
   kOpPruneCommit,
   kOpSetTStop,
   kOpResetSmax,
-  kOpMargBegin
+  kOpMargBegin,
+  kOpRollback,
+  kOpPruneAccount
 };
 
 template <typename Real>
@@ -217,7 +219,11 @@ __device__ __forceinline__ void scalar_op(const Dev<Real>& d, int op, double arg
   switch (op) {
     case kOpStepBegin:
       sb->run = (sb->status == 0 && sb->t < sb->t_stop) ? 1u : 0u;
-      sb->nb_old = sb->nb;
+      // Steps enqueued after a failed one keep its start state for the rollback.
+      if (sb->status == 0) {
+        sb->nb_old = sb->nb;
+        sb->smax_begin = sb->smax_bits;
+      }
       sb->ndeferred = 0;
       break;
     case kOpDt: {
@@ -227,6 +233,7 @@ __device__ __forceinline__ void scalar_op(const Dev<Real>& d, int op, double arg
         sb->run = 0;
         break;
       }
+      sb->deferred += sb->ndeferred;
       const double smax = bits_to_double(sb->smax_bits);
       const double rem = sb->t_stop - sb->t;
       double dt;
@@ -247,7 +254,13 @@ __device__ __forceinline__ void scalar_op(const Dev<Real>& d, int op, double arg
         sb->smax_bits = 0ull;
         sb->nb_prev = sb->nb;
         sb->nb_new = 0;
+        sb->sum_pre = sb->sum;
       }
+      break;
+    case kOpPruneAccount:
+      // After the survivors' sum set the normaliser z = V sum: the fraction
+      // of the mass present before the prune that it removed.
+      if (sb->prun && sb->sum_pre > 0.0) sb->pruned += 1.0 - sb->z / (d.vol * sb->sum_pre);
       break;
     case kOpPruneCommit:
       if (!sb->prun) break;
@@ -264,6 +277,18 @@ __device__ __forceinline__ void scalar_op(const Dev<Real>& d, int op, double arg
     case kOpMargBegin:
       sb->nb_new = 0;
       sb->overflow = 0;
+      break;
+    case kOpRollback:
+      // A grow that ran out of bricks, hashtable slots or coordinate range:
+      // back to the state at the start of that step (k_rollback restored the
+      // masks; links are rebuilt after this).
+      if (sb->status == kErrCapacity || sb->status == kErrRange) {
+        sb->nb = min(sb->nb_old, d.cap_b);
+        sb->smax_bits = sb->smax_begin;
+        sb->status = 0;
+        sb->run = 0;
+        sb->prun = 0;
+      }
       break;
     default:
       break;
@@ -379,6 +404,24 @@ template <int N, typename Real>
 __global__ void k_relink_all(Dev<Real> d, int gate) {
   if (!gate_open(d, gate)) return;
   link_range<N>(d, 0u, nb_of(d), false);
+}
+
+// Undo a grow that failed (status capacity or range): bricks created since the
+// step began are emptied and the older bricks get back the occupancy masks
+// they had then (held in abv: flux pass A, compaction and initialisation keep
+// it equal to the masks that the next step starts from).  Every done mask is
+// cleared, so the next grow re-examines every source; set semantics make that
+// give the same grid.  Density rows are untouched: created cells hold 0.
+template <typename Real>
+__global__ void k_rollback(Dev<Real> d) {
+  const Scalars* sb = d.sb;
+  if (sb->status != kErrCapacity && sb->status != kErrRange) return;
+  const uint32_t nb_old = min(sb->nb_old, d.cap_b), nb = max(min(sb->nb, d.cap_b), nb_old);
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t b = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x; b < nb; b += stride) {
+    d.mask[b] = b < nb_old ? d.abv[b] : 0ull;
+    d.done[b] = 0ull;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -570,6 +613,7 @@ __global__ __launch_bounds__(kWG) void k_init_write(Dev<Real> d) {
         if (lane == 0) {
           d.key[dst] = pack_key<N>(B);
           d.mask[dst] = m;
+          d.abv[dst] = m;
         }
         const bool in = (m >> lane) & 1ull;
         Real* P = d.P0;
@@ -1221,6 +1265,8 @@ __device__ __forceinline__ void flux_a_body(const Dev<Real>& d, const Dev<Real>*
   for (uint32_t b = rg.begin; b < rg.end; b += rg.step) {
     const BrickMeta<N> bm = meta_unpack<N>(meta);
     const Real p0 = P[static_cast<size_t>(b) * kLanes + lane];
+    // The masks after this step's grow are the next step's start masks.
+    if (lane == 0) d.abv[b] = bm.mask;
     Dev<Real> dv = d;
     reload_geometry(dv, dsrc);
     // Only the face layer of each neighbour is needed: every lane loads the
@@ -1571,6 +1617,232 @@ __global__ __launch_bounds__(kWG) void k_prune_mark(Dev<Real> d) {
 }
 
 // ---------------------------------------------------------------------------
+// Orthant grow and prune (grow_mode 2; Sec. 3.3, Figs. 2-3): a source cell
+// grows every combination of its downwind steps, at most one step per
+// dimension (up to 2^n - 1 cells, more where a cell has both a +e_j and a
+// -e_j downwind side), and a below-threshold cell survives a prune when any
+// combination of its upwind steps reaches a cell at or above p*.  The
+// candidate cells of a brick fall into the 3^n bricks at offsets in
+// {-1, 0, 1}^n; the grow pass gathers them per target brick in LDS, one
+// 64-bit lane mask per target, from a per-lane walk over the lane's own step
+// combinations, then resolves the targets lane-parallel like the pairwise
+// pass (links for axis and edge targets, the hashtable beyond).
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int pow3(int n) { return n == 0 ? 1 : 3 * pow3(n - 1); }
+
+// Next step combination after st (digits in {-1, 0, +1}): per dimension 0,
+// then +1 if allowed, then -1 if allowed, carrying into the next dimension.
+// False once every combination was visited.
+template <int N>
+__device__ __forceinline__ bool next_steps(int* st, const bool* plus, const bool* minus) {
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    if (st[j] == 0 && plus[j]) {
+      st[j] = 1;
+      return true;
+    }
+    if (st[j] != -1 && minus[j]) {
+      st[j] = -1;
+      return true;
+    }
+    st[j] = 0;
+  }
+  return false;
+}
+
+// Where lane `lane` lands after the steps st: the target brick's offset as a
+// base-3 index (digit j = offset_j + 1) and the lane in that brick.
+template <int N>
+__device__ __forceinline__ void step_target(int lane, const int* st, int* tidx, int* tlane) {
+  int t = 0, l = 0, w = 1;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const int side = brick_side(N, j);
+    const int a = ((lane >> brick_off(N, j)) & (side - 1)) + st[j];
+    const int o = a < 0 ? -1 : (a >= side ? 1 : 0);
+    t += (o + 1) * w;
+    w *= 3;
+    l |= (a - o * side) << brick_off(N, j);
+  }
+  *tidx = t;
+  *tlane = l;
+}
+
+// Brick at base-3 offset index k from brick b (coordinates B): through the
+// axis links for up to two non-zero offsets, else through the hashtable.
+// kNone if it does not exist (or is not yet linked).
+template <int N, typename Real>
+__device__ __forceinline__ uint32_t orthant_brick(const Dev<Real>& d, uint32_t b, const int64_t* B, int k) {
+  int off[N];
+  int nz = 0, j0 = -1, j1 = -1;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    off[j] = k % 3 - 1;
+    k /= 3;
+    if (off[j] != 0) {
+      j1 = j0 < 0 ? -1 : j;
+      j0 = j0 < 0 ? j : j0;
+      ++nz;
+    }
+  }
+  if (nz == 0) return b;
+  if (nz == 1) return nbr_of(d, b, j0, off[j0]);
+  if (nz == 2) {
+    uint32_t t = nbr_of(d, nbr_of(d, b, j0, off[j0]), j1, off[j1]);
+    if (t == kNone) t = nbr_of(d, nbr_of(d, b, j1, off[j1]), j0, off[j0]);
+    if (t != kNone) return t;
+  }
+  int64_t TB[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) TB[j] = B[j] + off[j];
+  if (!brick_in_range<N>(TB)) return kNone;
+  return hash_find(d, pack_key<N>(TB));
+}
+
+template <int N, int MODEL, typename Real>
+__device__ __forceinline__ void grow_orthant_body(const Dev<Real>& d, Slot sl) {
+  Scalars* sb = d.sb;
+  if (!sb->run) return;
+  const uint32_t nb_old = sb->nb_old;
+  const Real* P = cur_p(d);
+  const bool thr0 = !(d.thresh_rel > 0.0);
+  const Real pstar = uniform(static_cast<Real>(d.thresh_rel * sb->maxp));
+  const int lane = lane_id();
+  constexpr int NT = pow3(N), CENTRE = (pow3(N) - 1) / 2;
+  __shared__ u64 tbl_all[kWavesPerWG][NT];
+  u64* tbl = tbl_all[threadIdx.x >> 6];
+  double smax = 0.0;
+  u64 nscan = 0, ncreated = 0;
+  const WaveRange rg = wave_range(nb_old, sl);
+  for (uint32_t b = rg.begin; b < rg.end; b += rg.step) {
+    const u64 m = d.mask[b], dn = d.done[b];
+    if ((m & ~dn) == 0ull) continue;
+    const Real pv = P[static_cast<size_t>(b) * kLanes + lane];
+    const bool src = ((m >> lane) & 1ull) && (thr0 ? (pv != Real(0)) : (pv >= pstar));
+    const u64 S = ballot(src);
+    const u64 todo = S & ~dn;
+    if (todo == 0ull) continue;
+    if (lane == 0) {
+      d.done[b] = dn | S;
+      ++nscan;
+    }
+    for (int k = lane; k < NT; k += kLanes) tbl[k] = 0ull;
+    wave_lds_sync();
+    int64_t B[N];
+    unpack_key<N>(d.key[b], B);
+    int32_t ii[N];
+    double xc[N];
+    cell_of<N>(d, B, lane, ii, xc);
+    if ((todo >> lane) & 1ull) {
+      bool plus[N], minus[N];
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        plus[j] = face_vel_fwd<MODEL, N>(d, xc, ii, j) > 0.0;
+        minus[j] = face_vel<MODEL, N>(d, xc, ii, j) < 0.0;
+      }
+      int st[N];
+#pragma unroll
+      for (int j = 0; j < N; ++j) st[j] = 0;
+      while (next_steps<N>(st, plus, minus)) {
+        int ti, tl;
+        step_target<N>(lane, st, &ti, &tl);
+        __hip_atomic_fetch_or(&tbl[ti], 1ull << tl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+      }
+    }
+    wave_lds_sync();
+    if (lane == 0) tbl[CENTRE] &= ~m;
+    wave_lds_sync();
+    for (int k0 = 0; k0 < NT; k0 += kLanes) {
+      const int k = k0 + lane;
+      const u64 bits = k < NT ? tbl[k] : 0ull;
+      const uint32_t t = bits != 0ull ? orthant_brick<N>(d, b, B, k) : kNone;
+      const u64 made = (bits != 0ull && t != kNone) ? bits & ~atomicOr(&d.mask[t], bits) : 0ull;
+      u64 made_t = ballot(made != 0ull);
+      u64 hash_t = ballot(bits != 0ull && t == kNone);
+      auto target_brick = [&](int kk, int64_t* TB) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          TB[j] = B[j] + (kk % 3 - 1);
+          kk /= 3;
+        }
+      };
+      while (made_t != 0ull) {
+        const int kl = __builtin_ctzll(made_t);
+        made_t &= made_t - 1ull;
+        const u64 mk = readlane64(made, kl);
+        int64_t TB[N];
+        target_brick(k0 + kl, TB);
+        ncreated += static_cast<u64>(__popcll(mk));
+        smax = fmax(smax, created_speed<N, MODEL>(d, TB, mk, lane));
+      }
+      while (hash_t != 0ull) {
+        const int kl = __builtin_ctzll(hash_t);
+        hash_t &= hash_t - 1ull;
+        const u64 bk = readlane64(bits, kl);
+        int64_t TB[N];
+        target_brick(k0 + kl, TB);
+        smax = fmax(smax, add_cells<N, MODEL>(d, TB, kNone, bk, lane, &ncreated));
+      }
+    }
+    wave_lds_sync();
+  }
+  smax = wave_max(smax);
+  if (lane == 0 && smax > 0.0) atomicMax(&sb->smax_bits, double_to_bits(smax));
+  if (lane == 0 && nscan > 0) atomicAdd(&sb->grow_bricks, nscan);
+  if (lane == 0 && ncreated > 0) atomicAdd(&sb->inserted, ncreated);
+}
+template <int N, int MODEL, typename Real>
+__global__ __launch_bounds__(kWG) void k_grow_orthant(Dev<Real> d) {
+  grow_orthant_body<N, MODEL, Real>(d, hw_slot());
+}
+
+// Orthant prune marks: a present cell below p* keeps its bit if any
+// combination of its upwind steps (+e_j where the forward-face velocity is
+// negative, -e_j where the backward-face velocity is positive) reaches a cell
+// whose above-threshold bit is set.
+template <int N, int MODEL, typename Real>
+__global__ __launch_bounds__(kWG) void k_prune_mark_orthant(Dev<Real> d) {
+  Scalars* sb = d.sb;
+  if (!sb->prun) return;
+  const int lane = lane_id();
+  double smax = 0.0;
+  const WaveRange rg = wave_range(nb_of(d));
+  for (uint32_t b = rg.begin; b < rg.end; b += rg.step) {
+    const u64 m = d.mask[b];
+    const u64 A = d.abv[b];
+    const u64 below = m & ~A;
+    int64_t B[N];
+    unpack_key<N>(d.key[b], B);
+    int32_t ii[N];
+    double xc[N];
+    cell_of<N>(d, B, lane, ii, xc);
+    bool kept = false;
+    if ((below >> lane) & 1ull) {
+      bool plus[N], minus[N];
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        plus[j] = face_vel_fwd<MODEL, N>(d, xc, ii, j) < 0.0;
+        minus[j] = face_vel<MODEL, N>(d, xc, ii, j) > 0.0;
+      }
+      int st[N];
+#pragma unroll
+      for (int j = 0; j < N; ++j) st[j] = 0;
+      while (!kept && next_steps<N>(st, plus, minus)) {
+        int ti, tl;
+        step_target<N>(lane, st, &ti, &tl);
+        const uint32_t t = orthant_brick<N>(d, b, B, ti);
+        if (t != kNone && t < d.cap_b) kept = (d.abv[t] >> tl) & 1ull;
+      }
+    }
+    const u64 keep = A | (ballot(kept) & below);
+    if (lane == 0) d.mask[b] = keep;
+    if ((keep >> lane) & 1ull) smax = fmax(smax, cell_speed<MODEL, N>(d, xc, ii));
+  }
+  smax = wave_max(smax);
+  if (lane == 0 && smax > 0.0) atomicMax(&sb->smax_bits, double_to_bits(smax));
+}
+
+// ---------------------------------------------------------------------------
 // Reordering at prune: the bricks that kept a cell are sorted by the Morton
 // code of their brick coordinates (removed bricks sort last), so that the
 // axis neighbours of a brick sit close to it in memory and in time.  Stable
@@ -1754,12 +2026,10 @@ __global__ __launch_bounds__(kWG) void k_compact_finish(Dev<Real> d) {
   const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
   const uint64_t tid = blockIdx.x * uint64_t(blockDim.x) + threadIdx.x;
   for (uint64_t b = tid; b < nb_prev; b += stride) {
-    if (b < nb_new) {
-      d.key[b] = sc.key2[b];
-      d.mask[b] = sc.mask2[b];
-    } else {
-      d.mask[b] = 0ull;
-    }
+    const u64 m = b < nb_new ? sc.mask2[b] : 0ull;
+    if (b < nb_new) d.key[b] = sc.key2[b];
+    d.mask[b] = m;
+    d.abv[b] = m;
     d.done[b] = 0ull;
   }
   const uint64_t lo = uint64_t(nb_new) * kLanes, hi = uint64_t(nb_prev) * kLanes;
@@ -1932,7 +2202,10 @@ struct Ops {
     const Dev<Real>& d = D(p);
     k_scalar<Real><<<1, 64, 0, s>>>(d, kOpStepBegin, 0.0);
     pf->begin(kProfGrow, s);
-    k_grow<N, MODEL, Real><<<G, kWG, 0, s>>>(d);
+    if (d.grow_mode == 2)
+      k_grow_orthant<N, MODEL, Real><<<G, kWG, 0, s>>>(d);
+    else
+      k_grow<N, MODEL, Real><<<G, kWG, 0, s>>>(d);
     pf->end(s);
     pf->begin(kProfGrowFix, s);
     k_grow_fix<N, MODEL, Real><<<G, kWG, 0, s>>>(d);
@@ -1964,12 +2237,16 @@ struct Ops {
     pf->begin(kProfPrune, s);
     k_scalar<Real><<<1, 64, 0, s>>>(d, from_step ? kOpPruneBeginStep : kOpPruneBeginAlways, 0.0);
     k_prune_above<N, Real><<<G, kWG, 0, s>>>(d);
-    k_prune_mark<N, MODEL, Real><<<G, kWG, 0, s>>>(d);
+    if (d.grow_mode == 2)
+      k_prune_mark_orthant<N, MODEL, Real><<<G, kWG, 0, s>>>(d);
+    else
+      k_prune_mark<N, MODEL, Real><<<G, kWG, 0, s>>>(d);
     reorder(d, s, G);
     k_compact_finish<Real><<<G, kWG, 0, s>>>(d);
     k_scalar<Real><<<1, 64, 0, s>>>(d, kOpPruneCommit, 0.0);
     rebuild_links(d, s, G, kGatePrune);
     normalise_gated(d, s, G, kGatePrune);
+    k_scalar<Real><<<1, 64, 0, s>>>(d, kOpPruneAccount, 0.0);
     pf->end(s);
   }
 
@@ -1986,6 +2263,15 @@ struct Ops {
   }
 
   static void normalise(const void* p, hipStream_t s, uint32_t G, int gate) { normalise_gated(D(p), s, G, gate); }
+
+  static void rollback(const void* p, hipStream_t s, uint32_t G) {
+    const Dev<Real>& d = D(p);
+    k_rollback<Real><<<G, kWG, 0, s>>>(d);
+    k_scalar<Real><<<1, 64, 0, s>>>(d, kOpRollback, 0.0);
+    rebuild_links(d, s, G, kGateAlways);
+  }
+
+  static void relink(const void* p, hipStream_t s, uint32_t G) { rebuild_links(D(p), s, G, kGateAlways); }
 
   static void set_tstop(const void* p, hipStream_t s, double t_stop) {
     k_scalar<Real><<<1, 64, 0, s>>>(D(p), kOpSetTStop, t_stop);
@@ -2006,7 +2292,7 @@ struct Ops {
   static const KernelTable* table(int prec) {
     static const KernelTable t = {N,          MODEL,   prec,      &init_gaussian, &init_finish, &step,
                                   &prune,     &correct, &normalise, &set_tstop,     &marginals,   &probe,
-                                  &step_multi};
+                                  &step_multi, &rollback, &relink};
     return &t;
   }
 };

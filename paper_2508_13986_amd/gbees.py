@@ -53,6 +53,8 @@ class GbeesStats(ctypes.Structure):
         ("prunes", ctypes.c_int64),
         ("grow_bricks", ctypes.c_int64),
         ("inserted", ctypes.c_int64),
+        ("deferred", ctypes.c_int64),
+        ("mass_pruned", ctypes.c_double),
     ]
 
 
@@ -87,6 +89,7 @@ def lib():
         L.gbees_profile.argtypes = [vp, ctypes.c_int]
         L.gbees_profile_read.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
         L.gbees_destroy.argtypes = [vp]
+        L.gbees_resize.argtypes = [vp, i64, vp, ctypes.c_size_t]
         L.gbees_strerror.restype = ctypes.c_char_p
         L.gbees_strerror.argtypes = [ctypes.c_int]
         pp = ctypes.POINTER(ctypes.c_int32)
@@ -96,13 +99,14 @@ def lib():
         L.gbees_pool_info.argtypes = [vp, i64, ctypes.POINTER(GbeesReqInfo)]
         L.gbees_pool_result.argtypes = [vp, i64, i64, vp, vp, ctypes.POINTER(i64)]
         L.gbees_pool_release.argtypes = [vp, i64]
+        L.gbees_pool_group_size.argtypes = [vp, ctypes.c_int32]
         L.gbees_pool_clock.argtypes = [vp]
         L.gbees_pool_clock.restype = dbl
         L.gbees_pool_destroy.argtypes = [vp]
         for name in ("gbees_init_gaussian", "gbees_init_cells", "gbees_step", "gbees_correct", "gbees_marginals",
                      "gbees_export", "gbees_get_stats", "gbees_probe_stats", "gbees_profile",
-                     "gbees_profile_read", "gbees_destroy", "gbees_pool_create", "gbees_pool_submit",
-                     "gbees_pool_progress", "gbees_pool_info", "gbees_pool_result", "gbees_pool_release",
+                     "gbees_profile_read", "gbees_destroy", "gbees_resize", "gbees_pool_create", "gbees_pool_submit",
+                     "gbees_pool_progress", "gbees_pool_info", "gbees_pool_result", "gbees_pool_release", "gbees_pool_group_size",
                      "gbees_pool_destroy"):
             getattr(L, name).restype = ctypes.c_int
         _LIB = L
@@ -121,6 +125,7 @@ class GbeesReqInfo(ctypes.Structure):
         ("arena_bytes", ctypes.c_int64),
         ("cells", ctypes.c_int64),
         ("stats", GbeesStats),
+        ("resizes", ctypes.c_int64),
     ]
 
 
@@ -217,6 +222,20 @@ class Grid:
         s = GbeesStats()
         _check(lib().gbees_step(self._h, float(t_stop), int(max_steps), ctypes.byref(s)), "gbees_step")
         return _stats_dict(s)
+
+    def resize(self, max_cells):
+        """Move the grid into a new arena of capacity max_cells (the old one is dropped)."""
+        import torch
+
+        c = make_config(self.cfg, max_cells)
+        nbytes = int(lib().gbees_arena_bytes(ctypes.byref(c)))
+        if nbytes == 0:
+            raise GbeesError(E_ARG, "gbees_arena_bytes")
+        arena = torch.empty(nbytes, dtype=torch.uint8, device=self.arena.device)
+        _check(lib().gbees_resize(self._h, int(max_cells), ctypes.c_void_p(arena.data_ptr()), ctypes.c_size_t(nbytes)),
+               "gbees_resize")
+        self.arena = arena
+        self._c = c
 
     def correct(self, component, y, sigma):
         _check(lib().gbees_correct(self._h, int(component), float(y), float(sigma)), "gbees_correct")
@@ -315,7 +334,7 @@ class Pool:
         _check(lib().gbees_pool_info(self._h, int(rid), ctypes.byref(i)), "gbees_pool_info")
         st = {f: getattr(i.stats, f) for f, _ in GbeesStats._fields_}
         return {"status": i.status, "t_submit": i.t_submit, "t_admit": i.t_admit, "t_done": i.t_done,
-                "arena_bytes": i.arena_bytes, "cells": i.cells, "stats": st}
+                "arena_bytes": i.arena_bytes, "cells": i.cells, "stats": st, "resizes": i.resizes}
 
     def result(self, rid: int):
         """(idx int32[count, n], P float64[count]) of a finished request."""
@@ -329,6 +348,9 @@ class Pool:
         _check(lib().gbees_pool_result(self._h, int(rid), cnt.value, idx.ctypes.data_as(ctypes.c_void_p),
                                        P.ctypes.data_as(ctypes.c_void_p), ctypes.byref(cnt)), "gbees_pool_result")
         return idx, P
+
+    def group_size(self, k: int):
+        _check(lib().gbees_pool_group_size(self._h, int(k)), "gbees_pool_group_size")
 
     def release(self, rid: int):
         _check(lib().gbees_pool_release(self._h, int(rid)), "gbees_pool_release")

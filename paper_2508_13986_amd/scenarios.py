@@ -80,11 +80,21 @@ def l63_paper(thresh_rel=1e-5):
     """The paper's Lorenz '63 case (Sec. 5.1.1): (sigma, b, r) = (4, 1, 48) in
     its shifted form (standard form with rho = r and z_shift = r), mean
     (-11.5, -10, 9.5), unit variances, h = 0.5, a measurement y = x3 = -8 with
-    sigma_y = 1 at t = 1, horizon 2.  The threshold is not stated (read as 1e-5)."""
+    sigma_y = 1 at t = 1, horizon 2, time step 1.0 x CFL (Table 2).  The
+    threshold is not stated (read as 1e-5)."""
     d = _base(3, L63, lorenz63(sigma=4.0, rho=48.0, beta=1.0, z_shift=48.0), 0.5, [-11.5, -10.0, 9.5],
-              np.eye(3), thresh_rel, 2.0)
+              np.eye(3), thresh_rel, 2.0, cfl=1.0)
     d["measurements"] = [(1.0, 2, -8.0, 1.0)]
     return d
+
+
+def l96_paper(thresh_rel=1e-5, h=0.1):
+    """The paper's Lorenz '96 case (Sec. 5.1.2): n = 6, F = 4, mean
+    (F + 0.5, F, ..., F), standard deviation 0.2, h = 0.1 (half the standard
+    deviation, Table 2), horizon 1.3, no measurement, time step 1.0 x CFL.  The
+    threshold is not stated (read as 1e-5, as for Lorenz '63)."""
+    return _base(6, L96, lorenz96(4.0), h, [4.5, 4.0, 4.0, 4.0, 4.0, 4.0], 0.04 * np.eye(6), thresh_rel, 1.3,
+                 cfl=1.0)
 
 
 WORKLOADS = {
@@ -94,6 +104,7 @@ WORKLOADS = {
     "l96_6d_fp32": l96_6d_fp32,
     "l96_6d_downsampled": l96_6d_downsampled,
     "l63_paper": l63_paper,
+    "l96_paper": l96_paper,
 }
 
 

@@ -35,7 +35,10 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layout_matches_header():
     # gbees_config: 2 ints, 48+6+6+36 doubles, 3 doubles, 4 ints, int64, double
     assert ctypes.sizeof(G.GbeesConfig) == 8 + 8 * 96 + 24 + 16 + 8 + 8
-    assert ctypes.sizeof(G.GbeesStats) == 5 * 8 + 8 * 8
+    # gbees_stats: 5 doubles, 9 int64, 1 double
+    assert ctypes.sizeof(G.GbeesStats) == 5 * 8 + 9 * 8 + 8
+    # gbees_req_info: int32 (padded), 3 doubles, 2 int64, gbees_stats, int64
+    assert ctypes.sizeof(G.GbeesReqInfo) == 8 + 3 * 8 + 2 * 8 + ctypes.sizeof(G.GbeesStats) + 8
 
 
 def test_arena_sizing_and_validation():
@@ -77,7 +80,7 @@ def test_init_rejects_bad_arguments_before_touching_the_device():
 def test_pool_struct_layout_and_argument_checks():
     """Pool types match the header; calls reject bad arguments before any device work."""
     assert ctypes.sizeof(G.GbeesMeas) == 8 + 4 + 4 + 8 + 8  # t, component (+pad), y, sigma
-    assert ctypes.sizeof(G.GbeesReqInfo) == 8 + 3 * 8 + 8 + 8 + ctypes.sizeof(G.GbeesStats)
+    assert ctypes.sizeof(G.GbeesReqInfo) == 8 + 3 * 8 + 8 + 8 + ctypes.sizeof(G.GbeesStats) + 8
     L = G.lib()
     out = ctypes.c_void_p()
     fake = ctypes.c_void_p(0x1000)
@@ -93,5 +96,7 @@ def test_pool_struct_layout_and_argument_checks():
     cnt = ctypes.c_int64(0)
     assert L.gbees_pool_result(None, 1, 0, None, None, ctypes.byref(cnt)) == G.E_ARG
     assert L.gbees_pool_release(None, 1) == G.E_ARG
+    assert L.gbees_pool_group_size(None, 4) == G.E_ARG
+    assert L.gbees_resize(None, 1 << 16, fake, 1 << 20) == G.E_ARG
     assert L.gbees_pool_destroy(None) == G.E_ARG
     assert L.gbees_pool_clock(None) == 0.0

@@ -1,0 +1,86 @@
+"""GPU path against stored oracle results at sizes the oracle cannot run inside
+a test (tests/golden/, written by tests/golden/make_golden.py from the oracle
+alone): the Lorenz '63 corrections workload as specified, the Lorenz '96 6D
+benchmark grid at full size (1.1e7 initial cells) in the launch configuration
+the benchmark uses, and a 2.3e5-cell Lorenz '96 run through a prune.  Cell sets
+must match exactly; densities within 1e-12 of max P (tests/_golden.py)."""
+import numpy as np
+import pytest
+
+from paper_2508_13986_amd import scenarios as S
+
+import _golden
+
+pytestmark = pytest.mark.gpu
+
+# Capacity of the benchmark's Lorenz '96 job (cell slots), so that the grid is
+# stepped with the launch sizes the benchmark times.
+BENCH_MAX_CELLS = 64 * 8_000_000
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_2508_13986_amd import gbees
+    gbees.lib()
+    return gbees
+
+
+def _snap(gold, label):
+    for s in gold["snapshots"]:
+        if s["label"] == label:
+            return s
+    raise KeyError(label)
+
+
+def test_l63_corrections_as_specified(G):
+    """h = 0.25, cov 2 I, thr 1e-6, x1 corrections every 0.25 to t = 2."""
+    gold = _golden.load("l63_corrections")
+    cfg = S.l63_corrections()
+    thr = cfg["thresh_rel"]
+    grid = G.Grid.gaussian(cfg, max_cells=64 * 40_000)
+    gi, gp, t = grid.export()
+    _golden.check(gi, gp, t, _snap(gold, "init"), thr, label="C2 init")
+    for k, m in enumerate(cfg["measurements"]):
+        grid.step(m[0])
+        if k == 0:
+            _golden.check(*grid.export(), _snap(gold, f"t={m[0]}"), thr, label=f"C2 t={m[0]}")
+        grid.correct(m[1], m[2], m[3])
+        _golden.check(*grid.export(), _snap(gold, f"t={m[0]} corrected"), thr, label=f"C2 t={m[0]} corrected")
+    st = grid.stats()
+    assert st["steps"] == _snap(gold, "t=2.0 corrected")["steps"]
+    assert st["prunes"] == _snap(gold, "t=2.0 corrected")["prunes"]
+
+
+def test_l96_full_grid_first_steps(G):
+    """The benchmark grid (h = 0.25, thr 1e-7) at full size: initial grid and two
+    steps, with the benchmark's capacity and launch sizes (grid-stride loops over
+    about 20 bricks per wave)."""
+    gold = _golden.load("l96_6d_first_steps")
+    cfg = S.l96_6d()
+    thr = cfg["thresh_rel"]
+    grid = G.Grid.gaussian(cfg, max_cells=BENCH_MAX_CELLS)
+    _golden.check(*grid.export(), _snap(gold, "init"), thr, label="C3 init")
+    for k in (1, 2):
+        st = grid.step(cfg["t_end"], 1)
+        print(f"C3 step {k}: bricks {st['bricks']} deferred {st['deferred']} inserted {st['inserted']}", flush=True)
+        _golden.check(*grid.export(), _snap(gold, f"step {k}"), thr, label=f"C3 step {k}")
+    assert grid.stats()["bricks"] > 64 * 4096  # more bricks than waves: multi-brick grid-stride loops
+
+
+def test_l96_h04_through_prune(G):
+    """2.3e5 initial cells, 22 steps, pruned after step 20 (Morton reorder over
+    every sort chunk, compaction, rehash)."""
+    gold = _golden.load("l96_6d_h04_22steps")
+    cfg = S.l96_6d(h=0.4, thresh_rel=1e-5)
+    thr = cfg["thresh_rel"]
+    grid = G.Grid.gaussian(cfg, max_cells=64 * 200_000)
+    grid.step(cfg["t_end"], 20)
+    st = grid.stats()
+    print(f"h=0.4 after 20 steps: bricks {st['bricks']} deferred {st['deferred']} prunes {st['prunes']}", flush=True)
+    assert st["prunes"] == 1
+    _golden.check(*grid.export(), _snap(gold, "step 20 (pruned)"), thr, label="h=0.4 step 20")
+    grid.step(cfg["t_end"], 2)
+    _golden.check(*grid.export(), _snap(gold, "step 22"), thr, label="h=0.4 step 22")

@@ -38,6 +38,34 @@ def test_bc_identical_and_disjoint():
     assert M.bhattacharyya(idx, p, kde, [0.5] * 3) > 0.99
 
 
+@pytest.mark.parametrize("d", [3, 6])
+def test_exact_kde_matches_scipy(d):
+    """ExactKDE is the Scott-factor Gaussian KDE that scipy.stats.gaussian_kde
+    evaluates (same bandwidth rule, same kernel sum)."""
+    from scipy.stats import gaussian_kde
+    rng = np.random.default_rng(7 + d)
+    A = rng.standard_normal((d, d)) * 0.3 + np.eye(d)
+    x = A @ rng.standard_normal((d, 3000)) + 1.5
+    pts = x[:, :200].T + 0.1 * rng.standard_normal((200, d))
+    ours = M.ExactKDE(x).at_points(pts)
+    ref = gaussian_kde(x, bw_method="scott")(pts.T)
+    assert np.allclose(ours, ref, rtol=1e-10, atol=0.0)
+
+
+def test_bc_estimate_matches_exact_sum():
+    """The sampled BC estimate agrees with the full sum V sum sqrt(p q) within
+    four standard errors, on a grid Gaussian against a shifted kernel density."""
+    idx, p = _gauss_lattice(0.5, 10)
+    x = np.random.default_rng(8).standard_normal((3, 20_000)) + 0.3
+    kde = M.ExactKDE(x)
+    h = np.array([0.5] * 3)
+    q = kde.at_cells(idx, [0.0] * 3, h)
+    exact = 0.125 * np.sqrt(p * q).sum()
+    est, se = M.bc_estimate(idx, p, kde.at_cells, [0.0] * 3, h, 4000, seed=3)
+    assert abs(est - exact) <= 4 * se and se < 0.01
+    assert 0.9 < exact < 1.0
+
+
 def test_ensemble_matches_truth_integrator():
     """The vectorised ensemble integrator gives the single-trajectory truth
     integrator's state (both RK4, same step)."""
