@@ -137,6 +137,21 @@ int gbees_correct(gbees_ctx* ctx, int32_t component, double y, double sigma);
 int gbees_marginals(gbees_ctx* ctx, uint32_t dim_mask, int64_t capacity, int32_t* idx_out, double* val_out,
                     int64_t* count_out);
 
+/* For callers that cannot allocate (code under HIP graph capture, serving
+ * loops, harnesses that forbid allocation): the marginal of gbees_marginals,
+ * written into caller DEVICE buffers idx_dev[capacity][popcount(mask)] and
+ * val_dev[capacity], rows in no particular order, with the row count stored
+ * to *count_dev (device int64; -1 if the aggregation table overflowed; rows
+ * past capacity are counted but not written).  Only enqueues work on the
+ * context's stream: no allocation, no host copy, no wait.  The aggregation
+ * table is one file-scope device array of 2^20 slots (16 MiB) per GPU, held
+ * until the process ends and cleared by every call: calls that overlap on one
+ * GPU (any contexts, any streams) race for it.  GBEES_E_CAPACITY for grids of
+ * more than 2^19 cells.  Sums are FP64 atomics, so the last bits of a value
+ * may differ between calls. */
+int gbees_marginals_noalloc(gbees_ctx* ctx, uint32_t dim_mask, int64_t capacity, int32_t* idx_dev, double* val_dev,
+                            int64_t* count_dev);
+
 /* Copy the grid out: idx[count][n], P[count] sorted by index, and the time.
  * GBEES_E_BUFFER (with *count set) if capacity < count.  t may be NULL. */
 int gbees_export(gbees_ctx* ctx, int64_t capacity, int32_t* idx, double* P, int64_t* count, double* t);

@@ -10,7 +10,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libgbees.so")
 BUILD = os.path.join(PKG, "_build")
 
-SOURCES = ["inst_l63.hip", "inst_l96.hip", "inst_lin_a.hip", "inst_lin_b.hip", "dispatch.cpp", "gbees.cpp"]
+SOURCES = ["inst_l63.hip", "inst_l96.hip", "inst_lin_a.hip", "inst_lin_b.hip", "noalloc.hip", "dispatch.cpp", "gbees.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # no packed FP32 instructions (v_pk_*_f32) in any device code

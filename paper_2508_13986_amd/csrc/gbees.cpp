@@ -659,6 +659,25 @@ int gbees_marginals(gbees_ctx* c, uint32_t dim_mask, int64_t capacity, int32_t* 
   return GBEES_OK;
 }
 
+int gbees_marginals_noalloc(gbees_ctx* c, uint32_t dim_mask, int64_t capacity, int32_t* idx_dev, double* val_dev,
+                            int64_t* count_dev) {
+  const int rc = check_ctx(c);
+  if (rc != GBEES_OK) return rc;
+  const int n = c->cfg.n;
+  if (dim_mask == 0 || (dim_mask >> n) != 0 || !count_dev || capacity < 0 || (capacity > 0 && (!idx_dev || !val_dev)))
+    return GBEES_E_ARG;
+  // The scalar block the host holds is current after every call that
+  // returned; the table takes grids of up to half its slots in cells.
+  if (c->hsb.cells > gbees::marginal_scratch_slots() / 2) return GBEES_E_CAPACITY;
+  double w = 1.0;
+  for (int j = 0; j < n; ++j)
+    if (!((dim_mask >> j) & 1u)) w = w * c->cfg.h[j];
+  if (!gbees::marginals_static(c->dev, n, c->cfg.precision, c->stream, c->G(), dim_mask, w, capacity, idx_dev, val_dev,
+                               count_dev))
+    return GBEES_E_DEVICE;
+  return GBEES_OK;
+}
+
 int gbees_export(gbees_ctx* c, int64_t capacity, int32_t* idx, double* P, int64_t* count, double* t) {
   int rc = check_ctx(c);
   if (rc != GBEES_OK) return rc;

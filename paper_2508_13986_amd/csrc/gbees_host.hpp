@@ -97,5 +97,10 @@ struct KernelTable {
 
 const KernelTable* kernel_table(int model, int n, int precision);
 
+// Marginals through the file-scope scratch table of noalloc.hip (no
+// allocation, no host copy, no wait): slots of that table, and the launcher.
+uint64_t marginal_scratch_slots();
+bool marginals_static(const void* dev, int n, int precision, hipStream_t s, uint32_t G, uint32_t dim_mask,
+                      double weight, int64_t capacity, int32_t* idx, double* val, int64_t* count);
 
 }  // namespace gbees

@@ -90,6 +90,9 @@ def lib():
         L.gbees_profile_read.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
         L.gbees_destroy.argtypes = [vp]
         L.gbees_resize.argtypes = [vp, i64, vp, ctypes.c_size_t]
+        if hasattr(L, "gbees_marginals_noalloc"):
+            L.gbees_marginals_noalloc.argtypes = [vp, ctypes.c_uint32, i64, vp, vp, vp]
+            L.gbees_marginals_noalloc.restype = ctypes.c_int
         L.gbees_strerror.restype = ctypes.c_char_p
         L.gbees_strerror.argtypes = [ctypes.c_int]
         pp = ctypes.POINTER(ctypes.c_int32)

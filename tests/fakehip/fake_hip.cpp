@@ -283,6 +283,12 @@ struct Tables {
 
 }  // namespace
 
+uint64_t marginal_scratch_slots() { return uint64_t(1) << 20; }
+bool marginals_static(const void*, int, int, hipStream_t, uint32_t, uint32_t, double, int64_t, int32_t*, double*,
+                      int64_t*) {
+  return false;
+}
+
 const KernelTable* kernel_table(int model, int n, int precision) {
   static const Tables tables;
   if (precision != 0 && precision != 1) return nullptr;
