@@ -90,10 +90,19 @@ def grid_errors(a, b, cell_volume):
     """L1 = V * sum |Pa - Pb| and max |Pa - Pb| / max Pb over the union of the two
     grids (a missing cell counts as P = 0); a and b are (idx, P) exports."""
     import numpy as np
-    da = dict(zip(map(tuple, a[0]), a[1]))
-    db = dict(zip(map(tuple, b[0]), b[1]))
-    keys = set(da) | set(db)
-    diff = np.fromiter((da.get(k, 0.0) - db.get(k, 0.0) for k in keys), dtype=np.float64, count=len(keys))
+
+    def packed(idx):
+        bits = 63 // idx.shape[1]
+        key = np.zeros(len(idx), dtype=np.int64)
+        for j in range(idx.shape[1]):
+            key = (key << bits) + (idx[:, j].astype(np.int64) + (1 << (bits - 1)))
+        return key
+
+    ka, kb = packed(a[0]), packed(b[0])
+    keys = np.union1d(ka, kb)
+    diff = np.zeros(len(keys))
+    diff[np.searchsorted(keys, ka)] += a[1]
+    diff[np.searchsorted(keys, kb)] -= b[1]
     return {"l1": float(cell_volume * np.abs(diff).sum()), "max_rel": float(np.abs(diff).max() / np.abs(b[1]).max()),
             "cells": [len(a[0]), len(b[0])]}
 
@@ -127,9 +136,11 @@ def fp32_accuracy(G, S):
 
 
 def serving_bench(args):
-    """The serving stream through the device pool: one-at-a-time FP64 pass
-    (for the mean service time and the baseline), then all requests at once
-    (capacity), then Poisson arrivals at offered load rho = lambda E[S]."""
+    """The serving stream through the device pool: the same requests one at a
+    time on the plain FP64 path (for the mean service time and the baseline),
+    then all requests at once (burst), then Poisson arrivals at each offered
+    load rho = lambda E[S] of the sweep.  With --serving-precision 1 the pool
+    runs the FP32 form and reports its error against the FP64 results alone."""
     import numpy as np
     import torch
 
@@ -139,15 +150,21 @@ def serving_bench(args):
     torch.cuda.set_device(0)
     reqs, gaps = S.serving_requests(args.requests, seed=5)
     V.one_at_a_time(reqs[:1])  # warm-up: module load and first-touch of the kernels
-    alone = V.one_at_a_time(reqs)
+    fp32 = args.serving_precision == 1
+    alone = V.one_at_a_time(reqs, results=fp32)
     s_alone = np.array([a["seconds"] for a in alone])
     cu = float(sum(a["cell_updates"] for a in alone))
     pool_bytes = int(args.pool_gib * (1 << 30))
-    burst, mk_b = V.serve(reqs, np.zeros(len(reqs)), pool_bytes, args.max_active)
+    preqs = [dict(r, precision=1) for r in reqs] if fp32 else reqs
+    burst, mk_b = V.serve(preqs, np.zeros(len(reqs)), pool_bytes, args.max_active)
     sb = V.summarize(burst, mk_b)
-    lam = args.load / s_alone.mean()
-    pois, mk_p = V.serve(reqs, gaps / lam, pool_bytes, args.max_active)
-    sp = V.summarize(pois, mk_p)
+    sweep = []
+    for rho in args.loads:
+        lam = rho / s_alone.mean()
+        pois, mk_p = V.serve(preqs, gaps / lam, pool_bytes, args.max_active)
+        sweep.append(dict(V.summarize(pois, mk_p), offered_load=rho, rate_per_s=lam))
+        print(json.dumps({"offered_load": rho, "p50": sweep[-1]["p50_latency_s"], "p99": sweep[-1]["p99_latency_s"],
+                          "cell_updates_per_s": sweep[-1]["cell_updates_per_s"]}), file=sys.stderr, flush=True)
     n3 = sum(1 for r in reqs if r["n"] == 3)
     line = {
         "metric": "serving: aggregate cell-updates/s, mixed Lorenz-63/96 request stream",
@@ -160,18 +177,34 @@ def serving_bench(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32" if fp32 else "f64",
         "data": "synthetic (seeded request stream: priors, horizons, truth-trajectory measurements)",
         "config": {"workload": f"serving stream, seed 5: {len(reqs)} requests ({n3} Lorenz-63, {len(reqs) - n3} "
                                f"Lorenz-96 6D), horizons 0.5-2, 0-4 corrections each",
                    "max_active": args.max_active, "pool_gib": args.pool_gib, "parallelism": "single GPU"},
         "one_at_a_time": {"seconds": float(s_alone.sum()), "cell_updates_per_s": cu / float(s_alone.sum()),
                           "mean_service_s": float(s_alone.mean()), "p50_service_s": float(np.percentile(s_alone, 50)),
-                          "p99_service_s": float(np.percentile(s_alone, 99))},
+                          "p99_service_s": float(np.percentile(s_alone, 99)), "dtype": "f64"},
         "burst": sb,
-        "poisson": dict(sp, offered_load=args.load, rate_per_s=lam),
+        "poisson_sweep": sweep,
         "speedup_vs_one_at_a_time": sb["cell_updates_per_s"] / (cu / float(s_alone.sum())),
     }
+    if fp32:
+        # Error of each FP32 pool result against the same request's FP64 result
+        # alone (an extra, untimed burst that copies every result out).
+        with_res, _ = V.serve(preqs, np.zeros(len(reqs)), pool_bytes, args.max_active, results=True)
+        l1, mx = [], []
+        for r, a, b in zip(reqs, with_res, alone):
+            e = grid_errors(a["result"], b["result"], float(np.prod(r["h"][: r["n"]])))
+            l1.append(e["l1"])
+            mx.append(e["max_rel"])
+        l1, mx = np.array(l1), np.array(mx)
+        line["fp32_error_vs_fp64_alone"] = {
+            "l1_percentiles_50_90_99_max": [float(v) for v in np.percentile(l1, [50, 90, 99, 100])],
+            "max_rel_percentiles_50_90_99_max": [float(v) for v in np.percentile(mx, [50, 90, 99, 100])],
+            "requests_l1_above_1e-3": int((l1 > 1e-3).sum()),
+            "worst": [{"request": int(reqs[k]["request"]), "n": reqs[k]["n"], "h": reqs[k]["h"][0],
+                       "thresh_rel": reqs[k]["thresh_rel"], "l1": float(l1[k])} for k in np.argsort(l1)[-3:]]}
     print(json.dumps(line), flush=True)
 
 
@@ -252,7 +285,9 @@ def main():
     ap.add_argument("--max-cells", type=int, default=0, help="capacity in cell slots (default: per workload)")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the FP32-form error report")
     ap.add_argument("--requests", type=int, default=256, help="serving: requests in the stream")
-    ap.add_argument("--load", type=float, default=2.0, help="serving: offered load rho = lambda * E[service]")
+    ap.add_argument("--loads", type=float, nargs="+", default=[0.5, 1.0, 2.0, 4.0, 8.0],
+                    help="serving: offered loads rho = lambda * E[service] of the Poisson sweep")
+    ap.add_argument("--serving-precision", type=int, default=0, help="serving: 0 FP64, 1 FP32 form in the pool")
     ap.add_argument("--max-active", type=int, default=48, help="serving: requests running at once")
     ap.add_argument("--pool-gib", type=float, default=160.0, help="serving: arena of the pool")
     ap.add_argument("--cpu-budget", type=float, default=15.0)

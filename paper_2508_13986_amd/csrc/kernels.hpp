@@ -975,9 +975,14 @@ __device__ __forceinline__ void grow_body(const Dev<Real>& d, Slot sl) {
     // visited target by target for their S.  Targets without a link (a brick
     // that does not exist yet, or one created during this step) go through the
     // hashtable one at a time.
+    // Most targets already hold their candidate cells: a plain load of the
+    // target's mask settles those, and only cells still missing take the
+    // (slower, device-scope) atomic.  A stale mask only costs an atomic.
     u64 made0 = 0ull, made1 = 0ull;
-    if (bits0 != 0ull && t0 != kNone) made0 = bits0 & ~atomicOr(&d.mask[t0], bits0);
-    if (bits1 != 0ull && t1 != kNone) made1 = bits1 & ~atomicOr(&d.mask[t1], bits1);
+    u64 need0 = (bits0 != 0ull && t0 != kNone) ? bits0 & ~d.mask[t0] : 0ull;
+    u64 need1 = (bits1 != 0ull && t1 != kNone) ? bits1 & ~d.mask[t1] : 0ull;
+    if (need0 != 0ull) made0 = need0 & ~atomicOr(&d.mask[t0], need0);
+    if (need1 != 0ull) made1 = need1 & ~atomicOr(&d.mask[t1], need1);
     u64 made_t[2] = {ballot(made0 != 0ull), ballot(made1 != 0ull)};
     u64 hash_t[2] = {ballot(bits0 != 0ull && t0 == kNone), ballot(bits1 != 0ull && t1 == kNone)};
     auto target_brick = [&](int k, int64_t* TB) {
@@ -1272,7 +1277,7 @@ __device__ __forceinline__ void flux_a_body(const Dev<Real>& d, const Dev<Real>*
     // Only the face layer of each neighbour is needed: every lane loads the
     // neighbour cell of the boundary lane with its other coordinates.
     Real Fm[N], Fp[N];
-    u64 mp[N];
+    u64 mm[N], mp[N];
     static_for<N>([&](auto Jc) {
       constexpr int j = decltype(Jc)::value;
       constexpr uint32_t kRow = kLanes * sizeof(Real);
@@ -1281,6 +1286,7 @@ __device__ __forceinline__ void flux_a_body(const Dev<Real>& d, const Dev<Real>*
                        lane_with<N, j>(lane, brick_side(N, j) - 1) * sizeof(Real), Real(0));
       Fp[j] = row_load(row_rsrc(P + static_cast<size_t>(ip) * kLanes, kRow), lane_with<N, j>(lane, 0) * sizeof(Real),
                        Real(0));
+      mm[j] = load_const(d.mask + im);
       mp[j] = load_const(d.mask + ip);
     });
     const uint32_t bn = b + rg.step;
@@ -1309,9 +1315,13 @@ __device__ __forceinline__ void flux_a_body(const Dev<Real>& d, const Dev<Real>*
       T[j] = t_term(p0, pm, pp, ep, ub, uf);
       // A face layer's Q_l is read across the brick face only by the
       // downwind neighbour: the +e_j brick when the forward face velocity is
-      // positive, the -e_j brick when the backward one is negative.
-      // Stored per whole face layer (full cache lines, no partial writes).
-      const u64 want = ballot((lane_in(Dir<N, j, 1>::out) && uf > Real(0)) || (lane_in(Dir<N, j, -1>::out) && ub < Real(0))) & bm.mask;
+      // positive, the -e_j brick when the backward one is negative, and only
+      // where the cell across the face is in the grid (a face with a missing
+      // side carries no flux).  Stored per whole face layer (full cache
+      // lines, no partial writes).
+      const u64 across = (present_lanes<N, j, 1>(bm.mask, mp[j]) & Dir<N, j, 1>::out) |
+                         (present_lanes<N, j, -1>(bm.mask, mm[j]) & Dir<N, j, -1>::out);
+      const u64 want = ballot((lane_in(Dir<N, j, 1>::out) && uf > Real(0)) || (lane_in(Dir<N, j, -1>::out) && ub < Real(0))) & bm.mask & across;
       keep[j] = ((want & Dir<N, j, 1>::out) ? Dir<N, j, 1>::out : 0ull) | ((want & Dir<N, j, -1>::out) ? Dir<N, j, -1>::out : 0ull);
     });
     Real q[N];

@@ -59,7 +59,9 @@ def one_at_a_time(reqs, results=False):
 def serve(reqs, arrivals, pool_bytes, max_active=16, results=False, spin=2e-4):
     """Submit request k at time arrivals[k] (seconds from start) and drive the
     pool until every request has finished.  A request that outgrows its
-    capacity is resubmitted with four times as much, keeping its arrival time."""
+    capacity continues in a larger arena slice inside the pool; only if no
+    such slice is free does it fail, and it is then resubmitted with four
+    times the capacity, keeping its arrival time."""
     pool = G.Pool(pool_bytes, max_active)
     order = np.argsort(arrivals, kind="stable")
     t0 = pool.clock()
@@ -85,7 +87,8 @@ def serve(reqs, arrivals, pool_bytes, max_active=16, results=False, spin=2e-4):
                 else:
                     rec = {"latency": inf["t_done"] - t0 - arrivals[k], "queued": inf["t_admit"] - t0 - arrivals[k],
                            "cell_updates": inf["stats"]["cell_updates"], "cells": inf["cells"],
-                           "arena_bytes": inf["arena_bytes"], "retries": int(round(math.log(factor[k], 4)))}
+                           "arena_bytes": inf["arena_bytes"], "retries": int(round(math.log(factor[k], 4))),
+                           "resizes": inf["resizes"]}
                     if results:
                         rec["result"] = pool.result(rid)
                     done[k] = rec
@@ -103,4 +106,5 @@ def summarize(recs, makespan):
     return {"requests": len(recs), "makespan_s": makespan, "cell_updates": cu, "cell_updates_per_s": cu / makespan,
             "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
             "mean_queued_s": float(np.mean([r["queued"] for r in recs])),
-            "retries": int(sum(r["retries"] for r in recs))}
+            "retries": int(sum(r["retries"] for r in recs)),
+            "resized_in_pool": int(sum(1 for r in recs if r.get("resizes", 0) > 0))}

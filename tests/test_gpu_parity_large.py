@@ -67,7 +67,9 @@ def test_l96_full_grid_first_steps(G):
         st = grid.step(cfg["t_end"], 1)
         print(f"C3 step {k}: bricks {st['bricks']} deferred {st['deferred']} inserted {st['inserted']}", flush=True)
         _golden.check(*grid.export(), _snap(gold, f"step {k}"), thr, label=f"C3 step {k}")
-    assert grid.stats()["bricks"] > 64 * 4096  # more bricks than waves: multi-brick grid-stride loops
+    st = grid.stats()
+    assert st["bricks"] > 64 * 4096  # more bricks than waves: multi-brick grid-stride loops
+    assert st["deferred"] > 0  # inserts that found their brick still being created by another wave
 
 
 def test_l96_h04_through_prune(G):
@@ -81,6 +83,7 @@ def test_l96_h04_through_prune(G):
     st = grid.stats()
     print(f"h=0.4 after 20 steps: bricks {st['bricks']} deferred {st['deferred']} prunes {st['prunes']}", flush=True)
     assert st["prunes"] == 1
+    assert st["deferred"] > 0
     _golden.check(*grid.export(), _snap(gold, "step 20 (pruned)"), thr, label="h=0.4 step 20")
     grid.step(cfg["t_end"], 2)
     _golden.check(*grid.export(), _snap(gold, "step 22"), thr, label="h=0.4 step 22")
