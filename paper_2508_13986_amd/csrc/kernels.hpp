@@ -1252,6 +1252,120 @@ __device__ __forceinline__ void q_from_t(Real p0, const Real* c, const Real* T, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// LDS staging of pass A's inputs.  Each wave owns a slice of LDS holding, for
+// the brick it computes next, its own density row and the cells that each
+// axis neighbour offers across the shared face.  The slice is filled by
+// load-to-LDS global loads (16 bytes per lane, no vector registers held while
+// they are in flight), issued for the next brick as soon as the current
+// brick's values have been read out, so the memory round trip overlaps the
+// current brick's arithmetic.
+//
+// Slot 0 is the own row; slot 1 + 2j + s what the brick at (s ? +1 : -1) e_j
+// offers: its face layer next to this brick (a_j = side - 1 below, 0 above)
+// when that layer is made of whole 16-byte chunks, else its whole row.  A face
+// layer is stored compacted: the cell at in-brick position x sits at x with
+// the field of a_j removed.
+// ---------------------------------------------------------------------------
+template <int N, typename Real>
+struct FaceStage {
+  static constexpr int kCpc = 16 / static_cast<int>(sizeof(Real));  // cells per chunk
+  static constexpr int kRowChunks = kLanes / kCpc;
+  __host__ __device__ static constexpr bool layer(int j) { return brick_stride(N, j) >= kCpc; }
+  __host__ __device__ static constexpr int chunks(int j) { return layer(j) ? kRowChunks / brick_side(N, j) : kRowChunks; }
+  __host__ __device__ static constexpr int start(int slot) {
+    int c = slot > 0 ? kRowChunks : 0;
+    for (int k = 1; k < slot; ++k) c += chunks((k - 1) >> 1);
+    return c;
+  }
+  static constexpr int kChunks = start(2 * N + 1);
+  static constexpr int kInsts = (kChunks + kLanes - 1) / kLanes;
+  static constexpr int kBytes = kChunks * 16;
+};
+
+// What lane `lane` copies in load-to-LDS instruction t: the link lane of the
+// source brick in the meta word (-1: the brick itself, -2: nothing) and the
+// byte offset of its chunk in that brick's row.
+struct StageLane {
+  int link;
+  uint32_t off;
+};
+template <int N, typename Real>
+__device__ __forceinline__ StageLane stage_lane(int t, int lane) {
+  using F = FaceStage<N, Real>;
+  const int c = t * kLanes + lane;
+  StageLane r{c < F::kRowChunks ? -1 : -2, static_cast<uint32_t>(c) * 16u};
+  static_for<2 * N>([&](auto Kc) {
+    constexpr int k = decltype(Kc)::value, j = k >> 1, s = k & 1;
+    constexpr int lo = F::start(1 + k), hi = F::start(2 + k);
+    if (c >= lo && c < hi) {
+      const int q = c - lo;
+      r.link = k;
+      if constexpr (F::layer(j)) {
+        constexpr int off = brick_off(N, j), bits = brick_bits(N, j), v = s ? 0 : brick_side(N, j) - 1;
+        const int y = q * F::kCpc;
+        const int x = (y & ((1 << off) - 1)) | (v << off) | ((y >> off) << (off + bits));
+        r.off = static_cast<uint32_t>(x) * sizeof(Real);
+      } else {
+        r.off = static_cast<uint32_t>(q) * 16u;
+      }
+    }
+  });
+  return r;
+}
+
+typedef __attribute__((address_space(3))) char lds_char;
+// An LDS address the compiler cannot see through: values derived from it
+// (the per-copy LDS targets) are formed where they are used instead of being
+// hoisted out of the brick loop into scalar registers that then spill.
+__device__ __forceinline__ lds_char* lds_opaque(char* p) {
+  uint32_t a = static_cast<uint32_t>(reinterpret_cast<uintptr_t>((lds_char*)p));
+  asm volatile("" : "+s"(a));
+  return (lds_char*)static_cast<uintptr_t>(a);
+}
+// Starts the copies of brick b's staged inputs (mv: b's meta word) into the
+// wave's slice.  Missing neighbours read the permanently empty brick cap_b.
+template <int N, typename Real>
+__device__ __forceinline__ void stage_issue(const Real* P, uint32_t b, uint32_t mv, uint32_t cap_b, const StageLane* pl,
+                                            char* slice_in) {
+  using F = FaceStage<N, Real>;
+  lds_char* slice = lds_opaque(slice_in);
+#pragma unroll
+  for (int t = 0; t < F::kInsts; ++t) {
+    uint32_t idx = static_cast<uint32_t>(__shfl(static_cast<int>(mv), pl[t].link > 0 ? pl[t].link : 0));
+    idx = pl[t].link == -1 ? b : idx;
+    idx = idx == kNone ? cap_b : idx;
+    const char* src = reinterpret_cast<const char*>(P + static_cast<size_t>(idx) * kLanes) + pl[t].off;
+    if (t + 1 < F::kInsts || pl[t].link != -2)
+      __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(slice + t * kLanes * 16), 16, 0, 0);
+  }
+}
+
+// Byte position in the slice of the cell that the brick at (S ? +1 : -1) e_J
+// offers to lane `lane`.
+template <int N, typename Real, int J, int S>
+__device__ __forceinline__ uint32_t stage_pos(int lane) {
+  using F = FaceStage<N, Real>;
+  constexpr int off = brick_off(N, J), bits = brick_bits(N, J);
+  constexpr uint32_t base = static_cast<uint32_t>(F::start(1 + 2 * J + S)) * 16u;
+  if constexpr (F::layer(J)) {
+    const int y = (lane & ((1 << off) - 1)) | ((lane >> (off + bits)) << off);
+    return base + static_cast<uint32_t>(y) * sizeof(Real);
+  } else {
+    return base + static_cast<uint32_t>(lane_with<N, J>(lane, S ? 0 : brick_side(N, J) - 1)) * sizeof(Real);
+  }
+}
+template <typename Real>
+__device__ __forceinline__ Real slice_read(const char* slice, uint32_t pos) {
+  return *reinterpret_cast<const Real*>(slice + pos);
+}
+// The compiler does not order LDS reads against load-to-LDS copies, so the
+// two waits are explicit and are also compiler barriers for memory accesses:
+// copies into the slice have landed before it is read, and its reads have
+// returned before it is refilled.
+__device__ __forceinline__ void wait_stage_landed() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+__device__ __forceinline__ void wait_lds_reads() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
 // Flux pass A: transverse fluctuations and corrected states Q_l.
 template <int N, int MODEL, typename Real>
 __device__ __forceinline__ void flux_a_body(const Dev<Real>& d, const Dev<Real>* dsrc, Slot sl) {
@@ -1265,32 +1379,57 @@ __device__ __forceinline__ void flux_a_body(const Dev<Real>& d, const Dev<Real>*
 #pragma unroll
   for (int j = 0; j < N; ++j) c[j] = to_sgpr(static_cast<Real>(dt / (2.0 * d.h[j])));
   const int lane = lane_id();
+  using F = FaceStage<N, Real>;
+  __shared__ __align__(16) char stage_all[kWavesPerWG][F::kBytes];
+  char* slice = stage_all[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)];
+  StageLane pl[F::kInsts];
+#pragma unroll
+  for (int t = 0; t < F::kInsts; ++t) pl[t] = stage_lane<N, Real>(t, lane);
   const WaveRange rg = wave_range(nb, sl);
+  // The slice holds brick b's inputs while b is computed; meta holds b's
+  // links and meta_n those of the next brick.
   uint32_t meta = meta_fetch<N>(d, rg.begin < rg.end ? rg.begin : kNone, lane);
+  if (rg.begin < rg.end) stage_issue<N>(P, rg.begin, meta, d.cap_b, pl, slice);
+  uint32_t meta_n = meta_fetch<N>(d, rg.begin + rg.step < rg.end ? rg.begin + rg.step : kNone, lane);
+  // A brick's Q_l face layers are stored one iteration late, after the next
+  // copies have been issued: the wait for those copies then finds the stores
+  // long done instead of waiting for their completion.
+  Real qs[N];
+  uint32_t kb = 0;  // bit l: this lane stores Q_l of brick bprev
+  uint32_t bprev = kNone;
+  auto store_q = [&](uint32_t bq) {
+    Real* Qb = d.Q + static_cast<size_t>(bq) * N * kLanes;
+    static_for<N>([&](auto Lc) {
+      constexpr int l = decltype(Lc)::value;
+      if ((kb >> l) & 1u) Qb[l * kLanes + qpos<N, l>(lane)] = qs[l];
+    });
+  };
   for (uint32_t b = rg.begin; b < rg.end; b += rg.step) {
     const BrickMeta<N> bm = meta_unpack<N>(meta);
-    const Real p0 = P[static_cast<size_t>(b) * kLanes + lane];
+    wait_stage_landed();
+    const Real p0 = slice_read<Real>(slice, static_cast<uint32_t>(lane) * sizeof(Real));
+    Real Fm[N], Fp[N];
+    static_for<N>([&](auto Jc) {
+      constexpr int j = decltype(Jc)::value;
+      Fm[j] = slice_read<Real>(slice, stage_pos<N, Real, j, 0>(lane));
+      Fp[j] = slice_read<Real>(slice, stage_pos<N, Real, j, 1>(lane));
+    });
+    wait_lds_reads();
+    const uint32_t bn = b + rg.step;
+    if (bn < rg.end) stage_issue<N>(P, bn, meta_n, d.cap_b, pl, slice);
+    meta = meta_n;
+    meta_n = meta_fetch<N>(d, bn + rg.step < rg.end ? bn + rg.step : kNone, lane);
+    if (bprev != kNone) store_q(bprev);
     // The masks after this step's grow are the next step's start masks.
     if (lane == 0) d.abv[b] = bm.mask;
     Dev<Real> dv = d;
     reload_geometry(dv, dsrc);
-    // Only the face layer of each neighbour is needed: every lane loads the
-    // neighbour cell of the boundary lane with its other coordinates.
-    Real Fm[N], Fp[N];
     u64 mm[N], mp[N];
     static_for<N>([&](auto Jc) {
       constexpr int j = decltype(Jc)::value;
-      constexpr uint32_t kRow = kLanes * sizeof(Real);
-      const uint32_t im = bm.bm[j] != kNone ? bm.bm[j] : d.cap_b, ip = bm.bp[j] != kNone ? bm.bp[j] : d.cap_b;
-      Fm[j] = row_load(row_rsrc(P + static_cast<size_t>(im) * kLanes, kRow),
-                       lane_with<N, j>(lane, brick_side(N, j) - 1) * sizeof(Real), Real(0));
-      Fp[j] = row_load(row_rsrc(P + static_cast<size_t>(ip) * kLanes, kRow), lane_with<N, j>(lane, 0) * sizeof(Real),
-                       Real(0));
-      mm[j] = load_const(d.mask + im);
-      mp[j] = load_const(d.mask + ip);
+      mm[j] = load_const(d.mask + (bm.bm[j] != kNone ? bm.bm[j] : d.cap_b));
+      mp[j] = load_const(d.mask + (bm.bp[j] != kNone ? bm.bp[j] : d.cap_b));
     });
-    const uint32_t bn = b + rg.step;
-    meta = meta_fetch<N>(d, bn < rg.end ? bn : kNone, lane);
     int64_t B[N];
     unpack_key<N>(bm.key, B);
     int32_t ii[N];
@@ -1324,14 +1463,17 @@ __device__ __forceinline__ void flux_a_body(const Dev<Real>& d, const Dev<Real>*
       const u64 want = ballot((lane_in(Dir<N, j, 1>::out) && uf > Real(0)) || (lane_in(Dir<N, j, -1>::out) && ub < Real(0))) & bm.mask & across;
       keep[j] = ((want & Dir<N, j, 1>::out) ? Dir<N, j, 1>::out : 0ull) | ((want & Dir<N, j, -1>::out) ? Dir<N, j, -1>::out : 0ull);
     });
-    Real q[N];
-    q_from_t<N>(p0, c, T, q);
-    Real* Qb = d.Q + static_cast<size_t>(b) * N * kLanes;
+    q_from_t<N>(p0, c, T, qs);
+    const bool act = lane_in(bm.mask);
+    kb = 0;
     static_for<N>([&](auto Lc) {
       constexpr int l = decltype(Lc)::value;
-      if (lane_in(keep[l])) Qb[l * kLanes + qpos<N, l>(lane)] = lane_in(bm.mask) ? q[l] : Real(0);
+      qs[l] = act ? qs[l] : Real(0);
+      kb |= lane_in(keep[l]) ? (1u << l) : 0u;
     });
+    bprev = b;
   }
+  if (bprev != kNone) store_q(bprev);
 }
 template <int N, int MODEL, typename Real>
 __global__ __launch_bounds__(kWG, kFluxWavesPerEU) void k_flux_a(Dev<Real> d) {
