@@ -872,8 +872,29 @@ __device__ __forceinline__ uint32_t target_index(uint32_t t0, uint32_t t1, int k
 // Bricks whose density rows are fetched together by the grow scan.
 constexpr int kGrowBatch = 8;
 
-// Four waves per SIMD (measured faster than the three its register count would
-// otherwise allow: the scan is bound by memory latency).
+// Brick coordinates of target k of the brick with coordinates B.
+template <int N>
+__device__ __forceinline__ void target_coords(const int64_t* B, int k, int64_t* TB) {
+  int j = 0, s = 0, l = 0, r = 0;
+  const int kind = target_kind<N>(k, &j, &s, &l, &r);
+  // Static indexes only: a runtime index would put TB in scratch memory.
+#pragma unroll
+  for (int q = 0; q < N; ++q) TB[q] = B[q] + (kind >= 1 && q == j ? s : 0) + (kind == 2 && q == l ? r : 0);
+}
+
+// Grow in two phases per wave.  Phase one takes the bricks with new sources
+// one at a time: it marks their sources done and turns the sources' downwind
+// directions into candidate cells per target brick (the brick itself, its 2n
+// axis neighbours and its edge neighbours), which it appends to a list in LDS.
+// Phase two runs whenever the list holds a wave's worth of entries: each lane
+// resolves one (brick, target) entry through the links, reads the target's
+// mask and adds the missing cells with one atomic, so the dependent round
+// trips of many bricks are in flight together instead of one brick after
+// another.  Targets the links do not reach go through the hashtable, one at a
+// time.  The order in which targets receive their cells does not matter: the
+// grown set is the union over all sources of the pre-grow grid.
+//
+// Four waves per SIMD (measured faster than five or more, which spill).
 template <int N, int MODEL, typename Real>
 __device__ __forceinline__ void grow_body(const Dev<Real>& d, Slot sl) {
   Scalars* sb = d.sb;
@@ -885,24 +906,86 @@ __device__ __forceinline__ void grow_body(const Dev<Real>& d, Slot sl) {
   const Real pstar = uniform(static_cast<Real>(d.thresh_rel * sb->maxp));
   const int lane = lane_id();
   constexpr int NT = n_targets(N);
+  constexpr int kEnt = kLanes + NT;  // one resolution round plus one brick's targets
   __shared__ u64 tbl_all[kWavesPerWG][128];
-  __shared__ u64 work_all[kWavesPerWG][4 * kGrowBatch];
-  u64* tbl = tbl_all[threadIdx.x >> 6];
-  u64* work = work_all[threadIdx.x >> 6];
+  __shared__ u64 work_all[kWavesPerWG][5 * kGrowBatch];
+  __shared__ u64 ebits_all[kWavesPerWG][kEnt];
+  __shared__ u64 ekey_all[kWavesPerWG][kEnt];
+  __shared__ uint32_t eb_all[kWavesPerWG][kEnt];
+  __shared__ uint32_t ek_all[kWavesPerWG][kEnt];
+  const int wv = threadIdx.x >> 6;
+  u64* tbl = tbl_all[wv];
+  u64* work = work_all[wv];
+  u64* ebits = ebits_all[wv];
+  u64* ekey = ekey_all[wv];
+  uint32_t* eb = eb_all[wv];
+  uint32_t* ek = ek_all[wv];
+  uint32_t nent = 0;  // entries in the list (wave-uniform)
   double smax = 0.0;
   u64 nscan = 0, ncreated = 0;
 
+  // Phase two over the first `cnt` (<= 64) entries.
+  auto resolve = [&](uint32_t cnt) {
+    const bool live = static_cast<uint32_t>(lane) < cnt;
+    const u64 bits = live ? ebits[lane] : 0ull;
+    const uint32_t b = live ? eb[lane] : kNone;
+    const int k = live ? static_cast<int>(ek[lane]) : 0;
+    uint32_t t = kNone;
+    if (live) {
+      int j = 0, s = 0, l = 0, r = 0;
+      const int kind = target_kind<N>(k, &j, &s, &l, &r);
+      if (kind == 0) {
+        t = b;
+      } else {
+        // An edge target s e_j + r e_l is reached via the brick at s e_j, else
+        // via the one at r e_l.
+        const uint32_t h1 = nbr_of(d, b, j, s);
+        if (kind == 1) {
+          t = h1;
+        } else {
+          t = nbr_of(d, h1, l, r);
+          if (t == kNone) t = nbr_of(d, nbr_of(d, b, l, r), j, s);
+        }
+      }
+    }
+    // Most targets already hold their candidate cells: a plain load of the
+    // target's mask settles those, and only cells still missing take the
+    // (device-scope) atomic.  A stale mask only costs an atomic.
+    const u64 need = (live && t != kNone) ? bits & ~d.mask[t] : 0ull;
+    u64 made = 0ull;
+    if (need != 0ull) made = need & ~atomicOr(&d.mask[t], need);
+    u64 made_t = ballot(made != 0ull);
+    u64 hash_t = ballot(live && t == kNone);
+    while (made_t != 0ull) {
+      const int kl = __builtin_ctzll(made_t);
+      made_t &= made_t - 1ull;
+      const u64 mk = readlane64(made, kl);
+      int64_t B[N], TB[N];
+      unpack_key<N>(readlane64(ekey[lane], kl), B);
+      target_coords<N>(B, __builtin_amdgcn_readlane(k, kl), TB);
+      ncreated += static_cast<u64>(__popcll(mk));
+      smax = fmax(smax, created_speed<N, MODEL>(d, TB, mk, lane));
+    }
+    while (hash_t != 0ull) {
+      const int kl = __builtin_ctzll(hash_t);
+      hash_t &= hash_t - 1ull;
+      const u64 bk = readlane64(bits, kl);
+      int64_t B[N], TB[N];
+      unpack_key<N>(readlane64(ekey[lane], kl), B);
+      target_coords<N>(B, __builtin_amdgcn_readlane(k, kl), TB);
+      smax = fmax(smax, add_cells<N, MODEL>(d, TB, kNone, bk, lane, &ncreated));
+    }
+  };
 
-  // Grows brick b from its new sources `todo` (S: every source, dn: the done
-  // mask before this step, m: occupancy).
-  auto grow_brick = [&](uint32_t b, u64 m, u64 dn_new, u64 todo) {
+  // Phase one for brick b with key `key` (m: occupancy, dn_new: the done mask
+  // after this step, todo: the new sources).
+  auto grow_brick = [&](uint32_t b, u64 key, u64 m, u64 dn_new, u64 todo) {
     if (lane == 0) {
       d.done[b] = dn_new;
       ++nscan;
     }
-    const uint32_t axl = axis_links<N>(d, b, lane);
     int64_t B[N];
-    unpack_key<N>(d.key[b], B);
+    unpack_key<N>(key, B);
     int32_t ii[N];
     double xc[N];
     cell_of<N>(d, B, lane, ii, xc);
@@ -923,9 +1006,7 @@ __device__ __forceinline__ void grow_body(const Dev<Real>& d, Slot sl) {
     // then the edge neighbours.
     tbl[lane] = 0ull;
     tbl[lane + 64] = 0ull;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wave_lds_sync();
     u64 own = 0ull;
     u64 ax[2 * N];
 #pragma unroll
@@ -961,56 +1042,44 @@ __device__ __forceinline__ void grow_body(const Dev<Real>& d, Slot sl) {
 #pragma unroll
       for (int k = 0; k < 2 * N; ++k) tbl[1 + k] = ax[k];
     }
-    // Lane-parallel: resolve the targets that received candidates and keep the
-    // candidate cells not yet present.  (Wave-scope fence: lane 0 wrote the table.)
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wave_lds_sync();
+    // Append the targets that received candidates.
     const u64 bits0 = tbl[lane];
     const u64 bits1 = lane + 64 < NT ? tbl[lane + 64] : 0ull;
-    const uint32_t t0 = resolve_target<N>(d, b, lane, axl, bits0 != 0ull);
-    const uint32_t t1 = resolve_target<N>(d, b, lane + 64, axl, bits1 != 0ull);
-    // Targets reached through the links take their cells with one atomicOr per
-    // lane, all in flight together; the cells each of them gained are then
-    // visited target by target for their S.  Targets without a link (a brick
-    // that does not exist yet, or one created during this step) go through the
-    // hashtable one at a time.
-    // Most targets already hold their candidate cells: a plain load of the
-    // target's mask settles those, and only cells still missing take the
-    // (slower, device-scope) atomic.  A stale mask only costs an atomic.
-    u64 made0 = 0ull, made1 = 0ull;
-    u64 need0 = (bits0 != 0ull && t0 != kNone) ? bits0 & ~d.mask[t0] : 0ull;
-    u64 need1 = (bits1 != 0ull && t1 != kNone) ? bits1 & ~d.mask[t1] : 0ull;
-    if (need0 != 0ull) made0 = need0 & ~atomicOr(&d.mask[t0], need0);
-    if (need1 != 0ull) made1 = need1 & ~atomicOr(&d.mask[t1], need1);
-    u64 made_t[2] = {ballot(made0 != 0ull), ballot(made1 != 0ull)};
-    u64 hash_t[2] = {ballot(bits0 != 0ull && t0 == kNone), ballot(bits1 != 0ull && t1 == kNone)};
-    auto target_brick = [&](int k, int64_t* TB) {
-      int j = 0, s = 0, l = 0, r = 0;
-      const int kind = target_kind<N>(k, &j, &s, &l, &r);
-      // Static indexes only: a runtime index would put TB in scratch memory.
-#pragma unroll
-      for (int q = 0; q < N; ++q) TB[q] = B[q] + (kind >= 1 && q == j ? s : 0) + (kind == 2 && q == l ? r : 0);
-    };
-#pragma unroll
-    for (int half = 0; half < 2; ++half) {
-      while (made_t[half] != 0ull) {
-        const int kl = __builtin_ctzll(made_t[half]);
-        made_t[half] &= made_t[half] - 1ull;
-        const u64 made = readlane64(half ? made1 : made0, kl);
-        int64_t TB[N];
-        target_brick(kl + 64 * half, TB);
-        ncreated += static_cast<u64>(__popcll(made));
-        smax = fmax(smax, created_speed<N, MODEL>(d, TB, made, lane));
-      }
-      while (hash_t[half] != 0ull) {
-        const int kl = __builtin_ctzll(hash_t[half]);
-        hash_t[half] &= hash_t[half] - 1ull;
-        const u64 bits = readlane64(half ? bits1 : bits0, kl);
-        int64_t TB[N];
-        target_brick(kl + 64 * half, TB);
-        smax = fmax(smax, add_cells<N, MODEL>(d, TB, kNone, bits, lane, &ncreated));
-      }
+    const u64 nz0 = ballot(bits0 != 0ull), nz1 = ballot(bits1 != 0ull);
+    const u64 below = (1ull << lane) - 1ull;
+    if (bits0 != 0ull) {
+      const uint32_t at = nent + static_cast<uint32_t>(__popcll(nz0 & below));
+      ebits[at] = bits0;
+      ekey[at] = key;
+      eb[at] = b;
+      ek[at] = static_cast<uint32_t>(lane);
+    }
+    if (bits1 != 0ull) {
+      const uint32_t at = nent + static_cast<uint32_t>(__popcll(nz0) + __popcll(nz1 & below));
+      ebits[at] = bits1;
+      ekey[at] = key;
+      eb[at] = b;
+      ek[at] = static_cast<uint32_t>(lane + 64);
+    }
+    nent += static_cast<uint32_t>(__popcll(nz0) + __popcll(nz1));
+    wave_lds_sync();
+    while (nent >= static_cast<uint32_t>(kLanes)) {
+      resolve(kLanes);
+      // Move the remaining entries (fewer than NT) to the front: read them
+      // all before writing any (the ranges overlap for NT > 64).
+      const uint32_t rest = nent - kLanes;
+      const uint32_t i0 = static_cast<uint32_t>(lane), i1 = static_cast<uint32_t>(lane) + kLanes;
+      const bool m0 = i0 < rest, m1 = i1 < rest;
+      u64 vb0 = 0ull, vk0 = 0ull, vb1 = 0ull, vk1 = 0ull;
+      uint32_t b0 = 0, k0 = 0, b1 = 0, k1 = 0;
+      if (m0) { vb0 = ebits[kLanes + i0]; vk0 = ekey[kLanes + i0]; b0 = eb[kLanes + i0]; k0 = ek[kLanes + i0]; }
+      if (m1) { vb1 = ebits[kLanes + i1]; vk1 = ekey[kLanes + i1]; b1 = eb[kLanes + i1]; k1 = ek[kLanes + i1]; }
+      wave_lds_sync();
+      if (m0) { ebits[i0] = vb0; ekey[i0] = vk0; eb[i0] = b0; ek[i0] = k0; }
+      if (m1) { ebits[i1] = vb1; ekey[i1] = vk1; eb[i1] = b1; ek[i1] = k1; }
+      wave_lds_sync();
+      nent = rest;
     }
   };
 
@@ -1023,20 +1092,21 @@ __device__ __forceinline__ void grow_body(const Dev<Real>& d, Slot sl) {
   const RunRange rr = wave_runs(nb_old, sl);
   for (uint32_t r = rr.begin; r < rr.end; r += rr.step) {
     const uint32_t bl = r + static_cast<uint32_t>(lane);
-    u64 ml = 0ull, dl = 0ull;
+    u64 ml = 0ull, dl = 0ull, kyl = 0ull;
     if (static_cast<uint32_t>(lane) < rr.len && bl < rr.end) {
       ml = d.mask[bl];
       dl = d.done[bl];
+      kyl = d.key[bl];
     }
     u64 cand = ballot((ml & ~dl) != 0ull);
     while (cand != 0ull) {
       uint32_t bk[kGrowBatch];
-      u64 mk[kGrowBatch], dk[kGrowBatch];
+      u64 mk[kGrowBatch], dk[kGrowBatch], kk[kGrowBatch];
       Real pk[kGrowBatch];
 #pragma unroll
       for (int k = 0; k < kGrowBatch; ++k) {
         bk[k] = kNone;
-        mk[k] = dk[k] = 0ull;
+        mk[k] = dk[k] = kk[k] = 0ull;
         pk[k] = Real(0);
         if (cand != 0ull) {
           const int kl = __builtin_ctzll(cand);
@@ -1044,6 +1114,7 @@ __device__ __forceinline__ void grow_body(const Dev<Real>& d, Slot sl) {
           bk[k] = r + static_cast<uint32_t>(kl);
           mk[k] = readlane64(ml, kl);
           dk[k] = readlane64(dl, kl);
+          kk[k] = readlane64(kyl, kl);
           pk[k] = P[static_cast<size_t>(bk[k]) * kLanes + lane];
         }
       }
@@ -1056,27 +1127,28 @@ __device__ __forceinline__ void grow_body(const Dev<Real>& d, Slot sl) {
         const u64 todo = S & ~dk[k];
         if (todo != 0ull) {
           if (lane == 0) {
-            work[4 * nwork] = bk[k];
-            work[4 * nwork + 1] = mk[k];
-            work[4 * nwork + 2] = dk[k] | S;
-            work[4 * nwork + 3] = todo;
+            work[5 * nwork] = bk[k];
+            work[5 * nwork + 1] = mk[k];
+            work[5 * nwork + 2] = dk[k] | S;
+            work[5 * nwork + 3] = todo;
+            work[5 * nwork + 4] = kk[k];
           }
           ++nwork;
         }
       }
       if (nwork == 0) continue;
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      wave_lds_sync();
       for (int w = 0; w < nwork; ++w) {
-        const uint32_t b = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<uint32_t>(work[4 * w])));
-        const u64 m = readlane64(work[4 * w + 1], 0);
-        const u64 dn_new = readlane64(work[4 * w + 2], 0);
-        const u64 todo = readlane64(work[4 * w + 3], 0);
-        grow_brick(b, m, dn_new, todo);
+        const uint32_t b = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<uint32_t>(work[5 * w])));
+        const u64 m = readlane64(work[5 * w + 1], 0);
+        const u64 dn_new = readlane64(work[5 * w + 2], 0);
+        const u64 todo = readlane64(work[5 * w + 3], 0);
+        const u64 key = readlane64(work[5 * w + 4], 0);
+        grow_brick(b, key, m, dn_new, todo);
       }
     }
   }
+  if (nent > 0) resolve(nent);
   smax = wave_max(smax);
   if (lane == 0 && smax > 0.0) atomicMax(&sb->smax_bits, double_to_bits(smax));
   if (lane == 0 && nscan > 0) atomicAdd(&sb->grow_bricks, nscan);
