@@ -882,6 +882,76 @@ __device__ __forceinline__ void target_coords(const int64_t* B, int k, int64_t* 
   for (int q = 0; q < N; ++q) TB[q] = B[q] + (kind >= 1 && q == j ? s : 0) + (kind == 2 && q == l ? r : 0);
 }
 
+// The moves of grow: 2n axis moves (s e_j) and, per pair j < l, four edge
+// moves (s e_j + r e_l).  A move carries a source set (the new sources whose
+// downwind directions include it) to candidate cells in up to four target
+// bricks, one per quadrant of the brick: lanes that stay inside along both
+// axes (the brick itself), that leave along j only (the axis neighbour at
+// s e_j), along l only (the one at r e_l), or along both (the edge
+// neighbour).  Each quadrant is a lane mask and a lane shift, fixed by the
+// brick shape; the table below holds them per move so that every lane of a
+// wave can apply one move.
+template <int N>
+struct MoveTable {
+  static constexpr int kMoves = 2 * N + 2 * N * (N - 1);
+  u64 q[4][kMoves];       // quadrant lane masks
+  uint32_t sh[4][kMoves];  // left shift | right shift << 8 (one of them 0)
+  uint32_t tg[kMoves];     // target of quadrant i in byte i (0xFF: none)
+  uint32_t src[kMoves];    // source set index a | b << 8 (b = 0xFF: all lanes)
+};
+template <int N>
+__device__ __forceinline__ uint32_t shift_code(int k) {
+  return k >= 0 ? static_cast<uint32_t>(k) : static_cast<uint32_t>(-k) << 8;
+}
+template <int N, int J, int SI, int L, int RI>
+__device__ __forceinline__ void move_entry(MoveTable<N>& t, int m) {
+  using Dj = Dir<N, J, SI ? 1 : -1>;
+  if constexpr (L < 0) {
+    t.q[0][m] = Dj::in;
+    t.q[1][m] = Dj::out;
+    t.q[2][m] = t.q[3][m] = 0ull;
+    t.sh[0][m] = shift_code<N>(Dj::sh_in);
+    t.sh[1][m] = shift_code<N>(Dj::sh_out);
+    t.sh[2][m] = t.sh[3][m] = 0u;
+    t.tg[m] = 0u | static_cast<uint32_t>(1 + 2 * J + SI) << 8 | 0xFFu << 16 | 0xFFu << 24;
+    t.src[m] = static_cast<uint32_t>(2 * J + SI) | 0xFFu << 8;
+  } else {
+    using Dl = Dir<N, L, RI ? 1 : -1>;
+    constexpr int pair = [] {
+      int p = 0;
+      for (int a = 0; a < J; ++a) p += N - 1 - a;
+      return p + (L - J - 1);
+    }();
+    t.q[0][m] = Dj::in & Dl::in;
+    t.q[1][m] = Dj::out & Dl::in;
+    t.q[2][m] = Dj::in & Dl::out;
+    t.q[3][m] = Dj::out & Dl::out;
+    t.sh[0][m] = shift_code<N>(Dj::sh_in + Dl::sh_in);
+    t.sh[1][m] = shift_code<N>(Dj::sh_out + Dl::sh_in);
+    t.sh[2][m] = shift_code<N>(Dj::sh_in + Dl::sh_out);
+    t.sh[3][m] = shift_code<N>(Dj::sh_out + Dl::sh_out);
+    t.tg[m] = 0u | static_cast<uint32_t>(1 + 2 * J + SI) << 8 | static_cast<uint32_t>(1 + 2 * L + RI) << 16 |
+              static_cast<uint32_t>(1 + 2 * N + 4 * pair + 2 * SI + RI) << 24;
+    t.src[m] = static_cast<uint32_t>(2 * J + SI) | static_cast<uint32_t>(2 * L + RI) << 8;
+  }
+}
+// Fills the table (one workgroup; callers synchronise afterwards).
+template <int N>
+__device__ __forceinline__ void fill_moves(MoveTable<N>& t) {
+  if (threadIdx.x != 0) return;
+  static_for<2 * N>([&](auto Mc) {
+    constexpr int m = decltype(Mc)::value;
+    move_entry<N, m / 2, m % 2, -1, 0>(t, m);
+  });
+  static_for<N * (N - 1) / 2>([&](auto Pc) {
+    constexpr int p = decltype(Pc)::value, j = pair_j(N, p), l = pair_l(N, p);
+    static_for<4>([&](auto Cc) {
+      constexpr int c = decltype(Cc)::value;
+      move_entry<N, j, (c >> 1), l, (c & 1)>(t, 2 * N + 4 * p + c);
+    });
+  });
+}
+
 // Grow in two phases per wave.  Phase one takes the bricks with new sources
 // one at a time: it marks their sources done and turns the sources' downwind
 // directions into candidate cells per target brick (the brick itself, its 2n
@@ -913,7 +983,12 @@ __device__ __forceinline__ void grow_body(const Dev<Real>& d, Slot sl) {
   __shared__ u64 ekey_all[kWavesPerWG][kEnt];
   __shared__ uint32_t eb_all[kWavesPerWG][kEnt];
   __shared__ uint32_t ek_all[kWavesPerWG][kEnt];
+  __shared__ u64 ud_all[kWavesPerWG][2 * N];
+  __shared__ MoveTable<N> mt;
+  fill_moves<N>(mt);
+  __syncthreads();
   const int wv = threadIdx.x >> 6;
+  u64* ud = ud_all[wv];
   u64* tbl = tbl_all[wv];
   u64* work = work_all[wv];
   u64* ebits = ebits_all[wv];
@@ -1001,50 +1076,49 @@ __device__ __forceinline__ void grow_body(const Dev<Real>& d, Slot sl) {
       U[j] = ballot(up);
       D[j] = ballot(dw);
     }
-    // Candidate cells of every target brick (bit algebra on lane masks) into the
-    // wave's table: entry 0 the brick itself, 1 + 2j + si the axis neighbours,
-    // then the edge neighbours.
+    // Candidate cells of every target brick into the wave's table (entry 0 the
+    // brick itself, 1 + 2j + si the axis neighbours, then the edge
+    // neighbours): lane i applies move i (and i + 64), OR-ing its quadrants
+    // into the targets they reach; an edge target has only its own move.
     tbl[lane] = 0ull;
     tbl[lane + 64] = 0ull;
-    wave_lds_sync();
-    u64 own = 0ull;
-    u64 ax[2 * N];
-#pragma unroll
-    for (int k = 0; k < 2 * N; ++k) ax[k] = 0ull;
-    static_for<N>([&](auto Jc) {
-      constexpr int j = decltype(Jc)::value;
-      static_for<2>([&](auto Sc) {
-        constexpr int si = decltype(Sc)::value;
-        using Dj = Dir<N, j, si ? 1 : -1>;
-        const u64 src_js = si ? U[j] : D[j];
-        own |= lshc<Dj::sh_in>(src_js & Dj::in);
-        ax[2 * j + si] |= lshc<Dj::sh_out>(src_js & Dj::out);
-      });
-    });
-    static_for<N*(N - 1) / 2>([&](auto Pc) {
-      constexpr int pair = decltype(Pc)::value;
-      constexpr int j = pair_j(N, pair), l = pair_l(N, pair);
-      static_for<4>([&](auto Cc) {
-        constexpr int si = decltype(Cc)::value >> 1, ri = decltype(Cc)::value & 1;
-        using Dj = Dir<N, j, si ? 1 : -1>;
-        using Dl = Dir<N, l, ri ? 1 : -1>;
-        const u64 both = (si ? U[j] : D[j]) & (ri ? U[l] : D[l]);
-        if (both == 0ull) return;
-        own |= lshc<Dj::sh_in + Dl::sh_in>(both & Dj::in & Dl::in);
-        ax[2 * j + si] |= lshc<Dj::sh_out + Dl::sh_in>(both & Dj::out & Dl::in);
-        ax[2 * l + ri] |= lshc<Dj::sh_in + Dl::sh_out>(both & Dj::in & Dl::out);
-        const u64 dg = lshc<Dj::sh_out + Dl::sh_out>(both & Dj::out & Dl::out);
-        if (dg != 0ull && lane == 0) tbl[1 + 2 * N + 4 * pair + 2 * si + ri] = dg;
-      });
-    });
     if (lane == 0) {
-      tbl[0] = own & ~m;
 #pragma unroll
-      for (int k = 0; k < 2 * N; ++k) tbl[1 + k] = ax[k];
+      for (int j = 0; j < N; ++j) {
+        ud[2 * j] = D[j];
+        ud[2 * j + 1] = U[j];
+      }
     }
     wave_lds_sync();
-    // Append the targets that received candidates.
-    const u64 bits0 = tbl[lane];
+    constexpr int kMoves = MoveTable<N>::kMoves;
+#pragma unroll
+    for (int rnd = 0; rnd * kLanes < kMoves; ++rnd) {
+      const int mv = lane + rnd * kLanes;
+      if (mv < kMoves) {
+        const uint32_t sc = mt.src[mv];
+        const u64 sa = ud[sc & 0xFFu];
+        const u64 both = (sc >> 8) == 0xFFu ? sa : sa & ud[sc >> 8];
+        if (both != 0ull) {
+          const uint32_t tg = mt.tg[mv];
+#pragma unroll
+          for (int qd = 0; qd < 4; ++qd) {
+            const uint32_t sh = mt.sh[qd][mv];
+            const u64 v = ((both & mt.q[qd][mv]) << (sh & 0xFFu)) >> (sh >> 8);
+            const uint32_t k = (tg >> (8 * qd)) & 0xFFu;
+            if (v != 0ull && k != 0xFFu) {
+              if (qd == 3)
+                tbl[k] = v;
+              else
+                atomicOr(reinterpret_cast<unsigned long long*>(&tbl[k]), static_cast<unsigned long long>(v));
+            }
+          }
+        }
+      }
+    }
+    wave_lds_sync();
+    // Append the targets that received candidates (the brick itself: the
+    // cells it does not hold yet).
+    const u64 bits0 = lane == 0 ? tbl[0] & ~m : tbl[lane];
     const u64 bits1 = lane + 64 < NT ? tbl[lane + 64] : 0ull;
     const u64 nz0 = ballot(bits0 != 0ull), nz1 = ballot(bits1 != 0ull);
     const u64 below = (1ull << lane) - 1ull;
