@@ -1523,7 +1523,7 @@ __device__ __forceinline__ void flux_a_body(const Dev<Real>& d, const Dev<Real>*
   const double dt = load_const(&sb->dt);
   Real c[N];
 #pragma unroll
-  for (int j = 0; j < N; ++j) c[j] = to_sgpr(static_cast<Real>(dt / (2.0 * d.h[j])));
+  for (int j = 0; j < N; ++j) c[j] = static_cast<Real>(dt / (2.0 * d.h[j]));
   const int lane = lane_id();
   using F = FaceStage<N, Real>;
   __shared__ __align__(16) char stage_all[kWavesPerWG][F::kBytes];
