@@ -156,12 +156,12 @@ def serving_bench(args):
     cu = float(sum(a["cell_updates"] for a in alone))
     pool_bytes = int(args.pool_gib * (1 << 30))
     preqs = [dict(r, precision=1) for r in reqs] if fp32 else reqs
-    burst, mk_b = V.serve(preqs, np.zeros(len(reqs)), pool_bytes, args.max_active)
+    burst, mk_b = V.serve(preqs, np.zeros(len(reqs)), pool_bytes, args.max_active, group=args.group_size)
     sb = V.summarize(burst, mk_b)
     sweep = []
     for rho in args.loads:
         lam = rho / s_alone.mean()
-        pois, mk_p = V.serve(preqs, gaps / lam, pool_bytes, args.max_active)
+        pois, mk_p = V.serve(preqs, gaps / lam, pool_bytes, args.max_active, group=args.group_size)
         sweep.append(dict(V.summarize(pois, mk_p), offered_load=rho, rate_per_s=lam))
         print(json.dumps({"offered_load": rho, "p50": sweep[-1]["p50_latency_s"], "p99": sweep[-1]["p99_latency_s"],
                           "cell_updates_per_s": sweep[-1]["cell_updates_per_s"]}), file=sys.stderr, flush=True)
@@ -181,7 +181,7 @@ def serving_bench(args):
         "data": "synthetic (seeded request stream: priors, horizons, truth-trajectory measurements)",
         "config": {"workload": f"serving stream, seed 5: {len(reqs)} requests ({n3} Lorenz-63, {len(reqs) - n3} "
                                f"Lorenz-96 6D), horizons 0.5-2, 0-4 corrections each",
-                   "max_active": args.max_active, "pool_gib": args.pool_gib, "parallelism": "single GPU"},
+                   "max_active": args.max_active, "group_size": args.group_size or 4, "pool_gib": args.pool_gib, "parallelism": "single GPU"},
         "one_at_a_time": {"seconds": float(s_alone.sum()), "cell_updates_per_s": cu / float(s_alone.sum()),
                           "mean_service_s": float(s_alone.mean()), "p50_service_s": float(np.percentile(s_alone, 50)),
                           "p99_service_s": float(np.percentile(s_alone, 99)), "dtype": "f64"},
@@ -192,7 +192,8 @@ def serving_bench(args):
     if fp32:
         # Error of each FP32 pool result against the same request's FP64 result
         # alone (an extra, untimed burst that copies every result out).
-        with_res, _ = V.serve(preqs, np.zeros(len(reqs)), pool_bytes, args.max_active, results=True)
+        with_res, _ = V.serve(preqs, np.zeros(len(reqs)), pool_bytes, args.max_active, results=True,
+                              group=args.group_size)
         l1, mx = [], []
         for r, a, b in zip(reqs, with_res, alone):
             e = grid_errors(a["result"], b["result"], float(np.prod(r["h"][: r["n"]])))
@@ -290,6 +291,7 @@ def main():
     ap.add_argument("--serving-precision", type=int, default=0, help="serving: 0 FP64, 1 FP32 form in the pool")
     ap.add_argument("--max-active", type=int, default=48, help="serving: requests running at once")
     ap.add_argument("--pool-gib", type=float, default=160.0, help="serving: arena of the pool")
+    ap.add_argument("--group-size", type=int, default=0, help="serving: requests stepped together (0: the pool's 4)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-baseline-full", type=int, default=0, metavar="STEPS",

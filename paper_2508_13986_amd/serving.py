@@ -56,13 +56,16 @@ def one_at_a_time(reqs, results=False):
     return out
 
 
-def serve(reqs, arrivals, pool_bytes, max_active=16, results=False, spin=2e-4):
+def serve(reqs, arrivals, pool_bytes, max_active=16, results=False, spin=2e-4, group=0):
     """Submit request k at time arrivals[k] (seconds from start) and drive the
     pool until every request has finished.  A request that outgrows its
     capacity continues in a larger arena slice inside the pool; only if no
     such slice is free does it fail, and it is then resubmitted with four
-    times the capacity, keeping its arrival time."""
+    times the capacity, keeping its arrival time.  group > 0 sets the number
+    of requests stepped together by one driver (the pool's default otherwise)."""
     pool = G.Pool(pool_bytes, max_active)
+    if group > 0:
+        pool.group_size(group)
     order = np.argsort(arrivals, kind="stable")
     t0 = pool.clock()
     nxt, live, done = 0, {}, {}
