@@ -2217,30 +2217,53 @@ __global__ __launch_bounds__(kWG) void k_sort_hist(Dev<Real> d, int gate, int sh
 }
 
 // Exclusive scan of the digit-major histogram (256 x kSortWG entries).
+// Inclusive prefix sum over the wave (lane l gets the sum of lanes 0..l).
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
+#pragma unroll
+  for (int o = 1; o < kLanes; o <<= 1) {
+    const uint32_t u = static_cast<uint32_t>(__shfl_up(static_cast<int>(v), o));
+    v += lane >= o ? u : 0u;
+  }
+  return v;
+}
+
+// Offsets of the radix scatter: digit-major exclusive prefix of the histogram
+// (digit d, chunk w) -> sum over digits below d of their totals plus the
+// counts of digit d in chunks below w.  A wave takes a digit row at a time,
+// four chunks per lane (coalesced), with one wave-wide scan per row.
 template <typename Real>
 __global__ __launch_bounds__(kWG) void k_sort_scan(Dev<Real> d, int gate) {
+  static_assert(kSortWG == 4 * kLanes && kWG == 256, "one digit per thread, four chunks per lane");
   if (!gate_open(d, gate)) return;
   const SortScratch sc = sort_scratch(d);
-  __shared__ uint32_t tot[kWG];
-  uint32_t* row = sc.hist + threadIdx.x * kSortWG;  // thread t owns digit t
-  uint32_t s = 0;
-  for (int w = 0; w < kSortWG; ++w) s += row[w];
-  tot[threadIdx.x] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t acc = 0;
-    for (int k = 0; k < kWG; ++k) {
-      const uint32_t v = tot[k];
-      tot[k] = acc;
-      acc += v;
-    }
+  __shared__ uint32_t tot[256];
+  const int lane = lane_id(), w = threadIdx.x >> 6;
+  for (int dg = w; dg < 256; dg += kWavesPerWG) {
+    const uint32_t* row = sc.hist + static_cast<size_t>(dg) * kSortWG + 4 * lane;
+    uint32_t s = row[0] + row[1] + row[2] + row[3];
+    s = wave_incl_scan(s, lane);
+    if (lane == kLanes - 1) tot[dg] = s;
   }
   __syncthreads();
-  uint32_t acc = tot[threadIdx.x];
-  for (int w = 0; w < kSortWG; ++w) {
-    const uint32_t v = row[w];
-    row[w] = acc;
-    acc += v;
+  if (w == 0) {
+    const uint32_t a = tot[4 * lane], b = tot[4 * lane + 1], c = tot[4 * lane + 2], e = tot[4 * lane + 3];
+    const uint32_t sum = a + b + c + e;
+    const uint32_t ex = wave_incl_scan(sum, lane) - sum;
+    tot[4 * lane] = ex;
+    tot[4 * lane + 1] = ex + a;
+    tot[4 * lane + 2] = ex + a + b;
+    tot[4 * lane + 3] = ex + a + b + c;
+  }
+  __syncthreads();
+  for (int dg = w; dg < 256; dg += kWavesPerWG) {
+    uint32_t* row = sc.hist + static_cast<size_t>(dg) * kSortWG + 4 * lane;
+    const uint32_t a = row[0], b = row[1], c = row[2], e = row[3];
+    const uint32_t sum = a + b + c + e;
+    const uint32_t ex = wave_incl_scan(sum, lane) - sum + tot[dg];
+    row[0] = ex;
+    row[1] = ex + a;
+    row[2] = ex + a + b;
+    row[3] = ex + a + b + c;
   }
 }
 
