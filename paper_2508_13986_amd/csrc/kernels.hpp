@@ -752,17 +752,24 @@ __device__ __forceinline__ uint32_t nbr_of(const Dev<Real>& d, uint32_t b, int j
 // next brick's links, mask and key can be fetched while the current brick is
 // computed: lane 2j + s holds the link to the brick at (s ? +1 : -1) e_j, lanes
 // 2n, 2n + 1 the occupancy mask and lanes 2n + 2, 2n + 3 the key (low word
-// first).  b == kNone loads nothing.
+// first).  Each lane reads one 32-bit word at base + (b << shift), with its
+// base and shift fixed for the whole launch (MetaLane); b == kNone loads
+// nothing.
+struct MetaLane {
+  const char* base;
+  uint32_t shift;
+};
 template <int N, typename Real>
-__device__ __forceinline__ uint32_t meta_fetch(const Dev<Real>& d, uint32_t b, int lane) {
+__device__ __forceinline__ MetaLane meta_lane(const Dev<Real>& d, int lane) {
+  if (lane < 2 * N) return {reinterpret_cast<const char*>(d.nbr + static_cast<size_t>(lane) * d.cap_b), 2};
+  if (lane < 2 * N + 2) return {reinterpret_cast<const char*>(d.mask) + 4 * (lane - 2 * N), 3};
+  return {reinterpret_cast<const char*>(d.key) + 4 * (lane - 2 * N - 2), 3};
+}
+template <int N>
+__device__ __forceinline__ uint32_t meta_fetch(MetaLane ml, uint32_t b) {
+  constexpr u64 kMetaLanes = (1ull << (2 * N + 4)) - 1;
   uint32_t v = 0;
-  if (b != kNone && lane < 2 * N + 4) {
-    const uint32_t* src =
-        lane < 2 * N ? d.nbr + static_cast<size_t>(lane) * d.cap_b + b
-                     : (lane < 2 * N + 2 ? reinterpret_cast<const uint32_t*>(d.mask + b) + (lane - 2 * N)
-                                         : reinterpret_cast<const uint32_t*>(d.key + b) + (lane - 2 * N - 2));
-    v = *src;
-  }
+  if (b != kNone && lane_in(kMetaLanes)) v = *reinterpret_cast<const uint32_t*>(ml.base + (static_cast<size_t>(b) << ml.shift));
   return v;
 }
 template <int N>
@@ -1378,10 +1385,48 @@ __device__ __forceinline__ T opaque(T v) {
   return v;
 }
 
-// Transverse fluctuation T_j of one cell (see the gather form above).
+// acc + a * b (acc - a * b with NEG) in the lanes of the wave-uniform lane
+// mask `lanes`, acc in the others.  The FMA runs with the execution mask
+// narrowed to those lanes (lanes already inactive stay so), which does the
+// work of a select without its vector instructions (two for a double).
+template <bool NEG>
+__device__ __forceinline__ double fma_lanes(u64 lanes, double a, double b, double acc) {
+  u64 saved;
+  if constexpr (NEG)
+    asm("s_and_saveexec_b64 %1, %2\n\tv_fma_f64 %0, -%3, %4, %0\n\ts_mov_b64 exec, %1"
+        : "+v"(acc), "=&s"(saved)
+        : "s"(lanes), "v"(a), "v"(b)
+        : "scc");
+  else
+    asm("s_and_saveexec_b64 %1, %2\n\tv_fma_f64 %0, %3, %4, %0\n\ts_mov_b64 exec, %1"
+        : "+v"(acc), "=&s"(saved)
+        : "s"(lanes), "v"(a), "v"(b)
+        : "scc");
+  return acc;
+}
+template <bool NEG>
+__device__ __forceinline__ float fma_lanes(u64 lanes, float a, float b, float acc) {
+  u64 saved;
+  if constexpr (NEG)
+    asm("s_and_saveexec_b64 %1, %2\n\tv_fma_f32 %0, -%3, %4, %0\n\ts_mov_b64 exec, %1"
+        : "+v"(acc), "=&s"(saved)
+        : "s"(lanes), "v"(a), "v"(b)
+        : "scc");
+  else
+    asm("s_and_saveexec_b64 %1, %2\n\tv_fma_f32 %0, %3, %4, %0\n\ts_mov_b64 exec, %1"
+        : "+v"(acc), "=&s"(saved)
+        : "s"(lanes), "v"(a), "v"(b)
+        : "scc");
+  return acc;
+}
+
+// Transverse fluctuation T_j of one cell (see the gather form above); the
+// forward term only where the +e_j neighbour is in the grid (lanes `ep`).
+// Both flux passes compute it with this one function, so the corrected states
+// pass A stores and pass B recomputes for its own cells are the same bits.
 template <typename Real>
-__device__ __forceinline__ Real t_term(Real p0, Real pm, Real pp, bool ep, Real ub, Real uf) {
-  return rpos(ub) * (p0 - pm) + (ep ? rneg(uf) * (pp - p0) : Real(0));
+__device__ __forceinline__ Real t_term(Real p0, Real pm, Real pp, u64 ep, Real ub, Real uf) {
+  return fma_lanes<false>(ep, rneg(uf), pp - p0, rpos(ub) * (p0 - pm));
 }
 // Q_l = P - sum_{j != l} c_j T_j, accumulated term by term so that Q_l is
 // exactly P when every transverse T_j vanishes (with the threshold at zero,
@@ -1427,6 +1472,20 @@ struct FaceStage {
   static constexpr int kChunks = start(2 * N + 1);
   static constexpr int kInsts = (kChunks + kLanes - 1) / kLanes;
   static constexpr int kBytes = kChunks * 16;
+  // Lanes of copy instruction t that copy a chunk of the brick's own row, and
+  // lanes that copy nothing (past the last chunk).
+  __host__ __device__ static constexpr u64 own_lanes(int t) {
+    u64 m = 0;
+    for (int l = 0; l < kLanes; ++l)
+      if (t * kLanes + l < kRowChunks) m |= 1ull << l;
+    return m;
+  }
+  __host__ __device__ static constexpr u64 idle_lanes(int t) {
+    u64 m = 0;
+    for (int l = 0; l < kLanes; ++l)
+      if (t * kLanes + l >= kChunks) m |= 1ull << l;
+    return m;
+  }
 };
 
 // What lane `lane` copies in load-to-LDS instruction t: the link lane of the
@@ -1476,15 +1535,19 @@ __device__ __forceinline__ void stage_issue(const Real* P, uint32_t b, uint32_t 
                                             char* slice_in) {
   using F = FaceStage<N, Real>;
   lds_char* slice = lds_opaque(slice_in);
-#pragma unroll
-  for (int t = 0; t < F::kInsts; ++t) {
-    uint32_t idx = static_cast<uint32_t>(__shfl(static_cast<int>(mv), pl[t].link > 0 ? pl[t].link : 0));
-    idx = pl[t].link == -1 ? b : idx;
-    idx = idx == kNone ? cap_b : idx;
+  static_for<F::kInsts>([&](auto Tc) {
+    constexpr int t = decltype(Tc)::value;
+    constexpr u64 own = F::own_lanes(t), idle = F::idle_lanes(t);
+    uint32_t idx = b;
+    if constexpr (own != ~0ull) {
+      idx = static_cast<uint32_t>(__shfl(static_cast<int>(mv), pl[t].link > 0 ? pl[t].link : 0));
+      if constexpr (own != 0ull) idx = lane_in(own) ? b : idx;
+      idx = idx == kNone ? cap_b : idx;
+    }
     const char* src = reinterpret_cast<const char*>(P + static_cast<size_t>(idx) * kLanes) + pl[t].off;
-    if (t + 1 < F::kInsts || pl[t].link != -2)
+    if (idle == 0ull || lane_in(~idle))
       __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(slice + t * kLanes * 16), 16, 0, 0);
-  }
+  });
 }
 
 // Byte position in the slice of the cell that the brick at (S ? +1 : -1) e_J
@@ -1534,20 +1597,24 @@ __device__ __forceinline__ void flux_a_body(const Dev<Real>& d, const Dev<Real>*
   const WaveRange rg = wave_range(nb, sl);
   // The slice holds brick b's inputs while b is computed; meta holds b's
   // links and meta_n those of the next brick.
-  uint32_t meta = meta_fetch<N>(d, rg.begin < rg.end ? rg.begin : kNone, lane);
+  const MetaLane ml = meta_lane<N>(d, lane);
+  uint32_t meta = meta_fetch<N>(ml, rg.begin < rg.end ? rg.begin : kNone);
   if (rg.begin < rg.end) stage_issue<N>(P, rg.begin, meta, d.cap_b, pl, slice);
-  uint32_t meta_n = meta_fetch<N>(d, rg.begin + rg.step < rg.end ? rg.begin + rg.step : kNone, lane);
+  uint32_t meta_n = meta_fetch<N>(ml, rg.begin + rg.step < rg.end ? rg.begin + rg.step : kNone);
   // A brick's Q_l face layers are stored one iteration late, after the next
   // copies have been issued: the wait for those copies then finds the stores
   // long done instead of waiting for their completion.
   Real qs[N];
-  uint32_t kb = 0;  // bit l: this lane stores Q_l of brick bprev
+  // Wave-uniform: bit 2l set when brick bprev stores its Q_l layer next to
+  // the +e_l face, bit 2l + 1 when it stores the one next to the -e_l face.
+  uint32_t kb = 0;
   uint32_t bprev = kNone;
   auto store_q = [&](uint32_t bq) {
     Real* Qb = d.Q + static_cast<size_t>(bq) * N * kLanes;
     static_for<N>([&](auto Lc) {
       constexpr int l = decltype(Lc)::value;
-      if ((kb >> l) & 1u) Qb[l * kLanes + qpos<N, l>(lane)] = qs[l];
+      const u64 lanes = ((kb >> (2 * l)) & 1u ? Dir<N, l, 1>::out : 0ull) | ((kb >> (2 * l)) & 2u ? Dir<N, l, -1>::out : 0ull);
+      if (lane_in(lanes)) Qb[l * kLanes + qpos<N, l>(lane)] = qs[l];
     });
   };
   for (uint32_t b = rg.begin; b < rg.end; b += rg.step) {
@@ -1564,7 +1631,7 @@ __device__ __forceinline__ void flux_a_body(const Dev<Real>& d, const Dev<Real>*
     const uint32_t bn = b + rg.step;
     if (bn < rg.end) stage_issue<N>(P, bn, meta_n, d.cap_b, pl, slice);
     meta = meta_n;
-    meta_n = meta_fetch<N>(d, bn + rg.step < rg.end ? bn + rg.step : kNone, lane);
+    meta_n = meta_fetch<N>(ml, bn + rg.step < rg.end ? bn + rg.step : kNone);
     if (bprev != kNone) store_q(bprev);
     // The masks after this step's grow are the next step's start masks.
     if (lane == 0) d.abv[b] = bm.mask;
@@ -1582,7 +1649,7 @@ __device__ __forceinline__ void flux_a_body(const Dev<Real>& d, const Dev<Real>*
     double xc[N];
     cell_of<N>(dv, B, lane, ii, xc);
     Real T[N];
-    u64 keep[N];  // lanes whose Q_l is stored for the neighbour bricks
+    uint32_t kn = 0;  // the next value of kb
     static_for<N>([&](auto Jc) {
       constexpr int j = decltype(Jc)::value;
       Real pm, pp;
@@ -1594,7 +1661,7 @@ __device__ __forceinline__ void flux_a_body(const Dev<Real>& d, const Dev<Real>*
         pm = nbface<N, j, -1>(own_shift<N, j, -1>(p0, lane), Fm[j]);
         pp = nbface<N, j, 1>(own_shift<N, j, 1>(p0, lane), Fp[j]);
       }
-      const bool ep = lane_in(present_lanes<N, j, 1>(bm.mask, mp[j]));
+      const u64 ep = present_lanes<N, j, 1>(bm.mask, mp[j]);
       const Real ub = static_cast<Real>(face_vel<MODEL, N>(dv, xc, ii, j));
       const Real uf = static_cast<Real>(face_vel_fwd<MODEL, N>(dv, xc, ii, j));
       T[j] = t_term(p0, pm, pp, ep, ub, uf);
@@ -1607,16 +1674,13 @@ __device__ __forceinline__ void flux_a_body(const Dev<Real>& d, const Dev<Real>*
       const u64 across = (present_lanes<N, j, 1>(bm.mask, mp[j]) & Dir<N, j, 1>::out) |
                          (present_lanes<N, j, -1>(bm.mask, mm[j]) & Dir<N, j, -1>::out);
       const u64 want = ballot((lane_in(Dir<N, j, 1>::out) && uf > Real(0)) || (lane_in(Dir<N, j, -1>::out) && ub < Real(0))) & bm.mask & across;
-      keep[j] = ((want & Dir<N, j, 1>::out) ? Dir<N, j, 1>::out : 0ull) | ((want & Dir<N, j, -1>::out) ? Dir<N, j, -1>::out : 0ull);
+      kn |= ((want & Dir<N, j, 1>::out) ? 1u : 0u) << (2 * j);
+      kn |= ((want & Dir<N, j, -1>::out) ? 2u : 0u) << (2 * j);
     });
+    // Lanes of absent cells in a stored layer store their Q_l too: pass B
+    // uses a face value only where the cells on both sides are in the grid.
     q_from_t<N>(p0, c, T, qs);
-    const bool act = lane_in(bm.mask);
-    kb = 0;
-    static_for<N>([&](auto Lc) {
-      constexpr int l = decltype(Lc)::value;
-      qs[l] = act ? qs[l] : Real(0);
-      kb |= lane_in(keep[l]) ? (1u << l) : 0u;
-    });
+    kb = kn;
     bprev = b;
   }
   if (bprev != kNone) store_q(bprev);
@@ -1648,7 +1712,8 @@ __device__ __forceinline__ void flux_b_body(const Dev<Real>& d, const Dev<Real>*
   double vmax = 0.0, vsum = 0.0;
   uint32_t ncells = 0;  // wave-uniform
   const WaveRange rg = wave_range(nb, sl);
-  uint32_t meta = meta_fetch<N>(d, rg.begin < rg.end ? rg.begin : kNone, lane);
+  const MetaLane ml = meta_lane<N>(d, lane);
+  uint32_t meta = meta_fetch<N>(ml, rg.begin < rg.end ? rg.begin : kNone);
   for (uint32_t b = rg.begin; b < rg.end; b += rg.step) {
     const BrickMeta<N> bm = meta_unpack<N>(meta);
     const size_t o = static_cast<size_t>(b) * kLanes + lane;
@@ -1688,14 +1753,13 @@ __device__ __forceinline__ void flux_b_body(const Dev<Real>& d, const Dev<Real>*
       mp[l] = load_const(d.mask + ip);
     });
     const uint32_t bn = b + rg.step;
-    meta = meta_fetch<N>(d, bn < rg.end ? bn : kNone, lane);
-    const bool act = lane_in(bm.mask);
+    meta = meta_fetch<N>(ml, bn < rg.end ? bn : kNone);
     // This brick's own corrected states, as pass A computed them.
     Real T[N];
     static_for<N>([&](auto Lc) {
       constexpr int l = decltype(Lc)::value;
       T[l] = t_term(p0, nbval<N, l, -1>(p0, Pm[l], lane), nbval<N, l, 1>(p0, Pp[l], lane),
-                    lane_in(present_lanes<N, l, 1>(bm.mask, mp[l])), ub[l], uf[l]);
+                    present_lanes<N, l, 1>(bm.mask, mp[l]), ub[l], uf[l]);
     });
     Real q[N];
     q_from_t<N>(p0, c, T, q);
@@ -1706,8 +1770,10 @@ __device__ __forceinline__ void flux_b_body(const Dev<Real>& d, const Dev<Real>*
     Real acc = p0;
     static_for<N>([&](auto Lc) {
       constexpr int l = decltype(Lc)::value;
-      const bool em = lane_in(present_lanes<N, l, -1>(bm.mask, mm[l]));
-      const bool ep = lane_in(present_lanes<N, l, 1>(bm.mask, mp[l]));
+      // Faces of cells in the grid whose other side is in the grid too; the
+      // others carry no flux, and absent cells keep their 0.
+      const u64 em = present_lanes<N, l, -1>(bm.mask, mm[l]) & bm.mask;
+      const u64 ep = present_lanes<N, l, 1>(bm.mask, mp[l]) & bm.mask;
       const Real pm1 = nbval<N, l, -1>(p0r, Pm[l], lane);
       const Real pp1 = nbval<N, l, 1>(p0r, Pp[l], lane);
       Real qm, qp;
@@ -1730,10 +1796,11 @@ __device__ __forceinline__ void flux_b_body(const Dev<Real>& d, const Dev<Real>*
         fb += hr_term(ub[l], dth[l], p0r - pm1, ub[l] > Real(0) ? pm1 - pm2 : pp1 - p0r);
         ff += hr_term(uf[l], dth[l], pp1 - p0r, uf[l] > Real(0) ? p0r - pm1 : pp2 - pp1);
       }
-      if (em) acc = acc + dth[l] * fb;
-      if (ep) acc = acc - dth[l] * ff;
+      acc = fma_lanes<false>(em, dth[l], fb, acc);
+      acc = fma_lanes<true>(ep, dth[l], ff, acc);
     });
-    const Real out = act ? acc : Real(0);
+    // An absent cell's acc is its stored P, which is 0.
+    const Real out = acc;
     Pn[o] = out;
     // Absent cells hold 0: they leave the sum unchanged and cannot raise the
     // maximum above its start value 0.
