@@ -2296,41 +2296,55 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
 
 // Offsets of the radix scatter: digit-major exclusive prefix of the histogram
 // (digit d, chunk w) -> sum over digits below d of their totals plus the
-// counts of digit d in chunks below w.  A wave takes a digit row at a time,
-// four chunks per lane (coalesced), with one wave-wide scan per row.
+// counts of digit d in chunks below w.  One workgroup of 16 waves; each wave
+// owns 16 digit rows, four chunks per lane (coalesced).  All of a wave's rows
+// are loaded before any is used, so the kernel waits for memory about once
+// rather than once per row.
+constexpr int kScanWG = 1024;
+constexpr int kScanRows = 256 / (kScanWG / kLanes);  // digit rows per wave
 template <typename Real>
-__global__ __launch_bounds__(kWG) void k_sort_scan(Dev<Real> d, int gate) {
-  static_assert(kSortWG == 4 * kLanes && kWG == 256, "one digit per thread, four chunks per lane");
+__global__ __launch_bounds__(kScanWG) void k_sort_scan(Dev<Real> d, int gate) {
+  static_assert(kSortWG == 4 * kLanes, "four chunks per lane");
   if (!gate_open(d, gate)) return;
   const SortScratch sc = sort_scratch(d);
   __shared__ uint32_t tot[256];
   const int lane = lane_id(), w = threadIdx.x >> 6;
-  for (int dg = w; dg < 256; dg += kWavesPerWG) {
-    const uint32_t* row = sc.hist + static_cast<size_t>(dg) * kSortWG + 4 * lane;
-    uint32_t s = row[0] + row[1] + row[2] + row[3];
-    s = wave_incl_scan(s, lane);
-    if (lane == kLanes - 1) tot[dg] = s;
+  constexpr int kWaves = kScanWG / kLanes;
+  uint32_t v[kScanRows][4];
+#pragma unroll
+  for (int r = 0; r < kScanRows; ++r) {
+    const uint32_t* row = sc.hist + static_cast<size_t>(w + kWaves * r) * kSortWG + 4 * lane;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[r][q] = row[q];
+  }
+  uint32_t ex[kScanRows];  // exclusive prefix of this lane's chunks within the row
+#pragma unroll
+  for (int r = 0; r < kScanRows; ++r) {
+    const uint32_t sum = v[r][0] + v[r][1] + v[r][2] + v[r][3];
+    const uint32_t inc = wave_incl_scan(sum, lane);
+    ex[r] = inc - sum;
+    if (lane == kLanes - 1) tot[w + kWaves * r] = inc;
   }
   __syncthreads();
   if (w == 0) {
     const uint32_t a = tot[4 * lane], b = tot[4 * lane + 1], c = tot[4 * lane + 2], e = tot[4 * lane + 3];
     const uint32_t sum = a + b + c + e;
-    const uint32_t ex = wave_incl_scan(sum, lane) - sum;
-    tot[4 * lane] = ex;
-    tot[4 * lane + 1] = ex + a;
-    tot[4 * lane + 2] = ex + a + b;
-    tot[4 * lane + 3] = ex + a + b + c;
+    const uint32_t x = wave_incl_scan(sum, lane) - sum;
+    tot[4 * lane] = x;
+    tot[4 * lane + 1] = x + a;
+    tot[4 * lane + 2] = x + a + b;
+    tot[4 * lane + 3] = x + a + b + c;
   }
   __syncthreads();
-  for (int dg = w; dg < 256; dg += kWavesPerWG) {
+#pragma unroll
+  for (int r = 0; r < kScanRows; ++r) {
+    const int dg = w + kWaves * r;
     uint32_t* row = sc.hist + static_cast<size_t>(dg) * kSortWG + 4 * lane;
-    const uint32_t a = row[0], b = row[1], c = row[2], e = row[3];
-    const uint32_t sum = a + b + c + e;
-    const uint32_t ex = wave_incl_scan(sum, lane) - sum + tot[dg];
-    row[0] = ex;
-    row[1] = ex + a;
-    row[2] = ex + a + b;
-    row[3] = ex + a + b + c;
+    const uint32_t x = ex[r] + tot[dg];
+    row[0] = x;
+    row[1] = x + v[r][0];
+    row[2] = x + v[r][0] + v[r][1];
+    row[3] = x + v[r][0] + v[r][1] + v[r][2];
   }
 }
 
@@ -2547,7 +2561,7 @@ struct Ops {
     int flip = 0;
     for (int shift = 0; shift < 64; shift += 8, flip ^= 1) {
       k_sort_hist<Real><<<kSortWG, kWG, 0, s>>>(d, kGatePrune, shift, flip);
-      k_sort_scan<Real><<<1, kWG, 0, s>>>(d, kGatePrune);
+      k_sort_scan<Real><<<1, kScanWG, 0, s>>>(d, kGatePrune);
       k_sort_scatter<Real><<<kSortWG, kWG, 0, s>>>(d, kGatePrune, shift, flip);
     }
     k_sort_permute<Real><<<G, kWG, 0, s>>>(d, kGatePrune, flip);
