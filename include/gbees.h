@@ -194,7 +194,9 @@ const char* gbees_strerror(int code);
  * carved out (so cfg->max_cells sets its footprint).  Running requests of one
  * kind (model, dimension, precision) are stepped together, one launch per
  * kernel for all of them, by that kind's driver thread; each keeps its own
- * device state and workgroup count and gets the result it would get alone.
+ * device state and gets the result it would get alone, up to the rounding of
+ * its sums (a pooled grid's launches take more bricks per wave than a grid
+ * stepped alone, since the pool's grids share the device).
  * Requests leave the pool as soon as they finish, which frees their slot for
  * the next ones (and their slice once the result was taken).  The pool
  * allocates no device memory; it owns a HIP stream per group of requests and

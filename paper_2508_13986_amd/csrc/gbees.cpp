@@ -189,8 +189,16 @@ bool spd_inverse(int n, const double* a_in, double* inv) {
   return true;
 }
 
-uint32_t grid_for(uint64_t bricks) {
-  uint64_t g = (bricks + 2 * gbees::kWavesPerWG - 1) / (2 * gbees::kWavesPerWG);
+// Workgroups of a grid-stride launch over `bricks` bricks: about `per_wave`
+// bricks per wave, but no fewer than 256 workgroups (or one per two waves'
+// worth of bricks, if that is fewer), so that a small grid still spreads over
+// the chip; a multiple of 8 (one run per XCD), at most kMaxWG.  Fewer, longer
+// waves amortise each wave's start (its first loads are not overlapped) and
+// leave room on the chip for other streams' launches.
+uint32_t grid_for(uint64_t bricks, uint32_t per_wave) {
+  const uint64_t per_wg = static_cast<uint64_t>(per_wave) * gbees::kWavesPerWG;
+  const uint64_t fine = (bricks + 2 * gbees::kWavesPerWG - 1) / (2 * gbees::kWavesPerWG);
+  uint64_t g = std::max<uint64_t>((bricks + per_wg - 1) / per_wg, std::min<uint64_t>(fine, 256));
   g = (g + 7) / 8 * 8;
   return static_cast<uint32_t>(std::min<uint64_t>(std::max<uint64_t>(g, 8), gbees::kMaxWG));
 }
@@ -209,11 +217,16 @@ struct gbees_ctx {
   Scalars hsb;
   int status = GBEES_OK;
   uint32_t nb_est = 64;
+  // Bricks per wave of the grid-stride launches: 8 for a grid that has the
+  // device to itself; the serving pool uses 16, since its grids share the
+  // device (measured on the serving stream: 8 per wave gave the best time for
+  // requests run one at a time, 16 the best burst through the pool).
+  uint32_t wave_bricks = 8;
   int64_t host_steps = 0;
   int batch = 4;
   gbees::Profiler prof;
 
-  uint32_t G() const { return grid_for(std::max<uint32_t>(nb_est, 64)); }
+  uint32_t G() const { return grid_for(std::max<uint32_t>(nb_est, 64), wave_bricks); }
 
   int sync_read() {
     if (hipMemcpyAsync(&hsb, base + L.sb, sizeof(Scalars), hipMemcpyDeviceToHost, stream) != hipSuccess)
@@ -925,9 +938,13 @@ struct Runner {
 // driver thread steps the running requests of its group with shared launches
 // (KernelTable::step_multi), so K steps of R grids cost 7K launches instead of
 // 7KR.  Each grid keeps its own workgroup count and device state, so it
-// computes exactly what it would compute alone; only the number of steps per
-// batch (the smallest any member asks for) is shared, and steps past a grid's
-// stop time are no-ops on the device.
+// computes what it would compute alone with that workgroup count; only the
+// number of steps per batch (the smallest any member asks for) is shared, and
+// steps past a grid's stop time are no-ops on the device.  A pooled grid's
+// launches use 16 bricks per wave (8 alone): the same cells and densities up to
+// the rounding of its sums, which are partitioned over other workgroups.
+constexpr uint32_t kPoolWaveBricks = 16;  // bricks per wave of a pooled grid's launches
+
 struct PoolGroup {
   int model = 0, n = 0, precision = 0;
   int members = 0;  // admitted and not finished (guarded by the pool mutex)
@@ -1078,6 +1095,7 @@ struct gbees_pool {
         }
         Runner x{id, r, nullptr, 0};
         const int rc = init_gaussian_begin(&r->cfg, base + r->off, r->bytes, g.stream, &x.c);
+        if (x.c) x.c->wave_bricks = kPoolWaveBricks;
         r->ctx = x.c;
         if (rc != GBEES_OK) {
           leave(g, x, rc);
