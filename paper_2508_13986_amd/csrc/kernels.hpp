@@ -906,57 +906,59 @@ struct MoveTable {
   uint32_t tg[kMoves];     // target of quadrant i in byte i (0xFF: none)
   uint32_t src[kMoves];    // source set index a | b << 8 (b = 0xFF: all lanes)
 };
+// The table of a brick shape, built at compile time: entry m < 2n is the axis
+// move s e_j (j = m / 2, s = +1 for odd m), then four edge moves per pair
+// j < l in pair order (s, r = -1, -1; -1, +1; +1, -1; +1, +1).  Quadrant 0
+// keeps the lanes that stay inside along both axes, 1 those that leave along
+// j only, 2 along l only, 3 along both; a shift is coded as left | right << 8.
 template <int N>
-__device__ __forceinline__ uint32_t shift_code(int k) {
-  return k >= 0 ? static_cast<uint32_t>(k) : static_cast<uint32_t>(-k) << 8;
-}
-template <int N, int J, int SI, int L, int RI>
-__device__ __forceinline__ void move_entry(MoveTable<N>& t, int m) {
-  using Dj = Dir<N, J, SI ? 1 : -1>;
-  if constexpr (L < 0) {
-    t.q[0][m] = Dj::in;
-    t.q[1][m] = Dj::out;
-    t.q[2][m] = t.q[3][m] = 0ull;
-    t.sh[0][m] = shift_code<N>(Dj::sh_in);
-    t.sh[1][m] = shift_code<N>(Dj::sh_out);
-    t.sh[2][m] = t.sh[3][m] = 0u;
-    t.tg[m] = 0u | static_cast<uint32_t>(1 + 2 * J + SI) << 8 | 0xFFu << 16 | 0xFFu << 24;
-    t.src[m] = static_cast<uint32_t>(2 * J + SI) | 0xFFu << 8;
-  } else {
-    using Dl = Dir<N, L, RI ? 1 : -1>;
-    constexpr int pair = [] {
-      int p = 0;
-      for (int a = 0; a < J; ++a) p += N - 1 - a;
-      return p + (L - J - 1);
-    }();
-    t.q[0][m] = Dj::in & Dl::in;
-    t.q[1][m] = Dj::out & Dl::in;
-    t.q[2][m] = Dj::in & Dl::out;
-    t.q[3][m] = Dj::out & Dl::out;
-    t.sh[0][m] = shift_code<N>(Dj::sh_in + Dl::sh_in);
-    t.sh[1][m] = shift_code<N>(Dj::sh_out + Dl::sh_in);
-    t.sh[2][m] = shift_code<N>(Dj::sh_in + Dl::sh_out);
-    t.sh[3][m] = shift_code<N>(Dj::sh_out + Dl::sh_out);
-    t.tg[m] = 0u | static_cast<uint32_t>(1 + 2 * J + SI) << 8 | static_cast<uint32_t>(1 + 2 * L + RI) << 16 |
-              static_cast<uint32_t>(1 + 2 * N + 4 * pair + 2 * SI + RI) << 24;
-    t.src[m] = static_cast<uint32_t>(2 * J + SI) | static_cast<uint32_t>(2 * L + RI) << 8;
+constexpr MoveTable<N> make_moves() {
+  MoveTable<N> t{};
+  auto out = [](int j, int s) { return s > 0 ? lanes_at(N, j, brick_side(N, j) - 1) : lanes_at(N, j, 0); };
+  auto sh_in = [](int j, int s) { return s * brick_stride(N, j); };
+  auto sh_out = [](int j, int s) { return -s * (brick_side(N, j) - 1) * brick_stride(N, j); };
+  auto code = [](int k) { return k >= 0 ? static_cast<uint32_t>(k) : static_cast<uint32_t>(-k) << 8; };
+  int m = 0;
+  for (int j = 0; j < N; ++j)
+    for (int si = 0; si < 2; ++si, ++m) {
+      const int s = si ? 1 : -1;
+      t.q[0][m] = ~out(j, s);
+      t.q[1][m] = out(j, s);
+      t.sh[0][m] = code(sh_in(j, s));
+      t.sh[1][m] = code(sh_out(j, s));
+      t.tg[m] = static_cast<uint32_t>(1 + 2 * j + si) << 8 | 0xFFu << 16 | 0xFFu << 24;
+      t.src[m] = static_cast<uint32_t>(2 * j + si) | 0xFFu << 8;
+    }
+  for (int p = 0; p < N * (N - 1) / 2; ++p) {
+    const int j = pair_j(N, p), l = pair_l(N, p);
+    for (int c = 0; c < 4; ++c, ++m) {
+      const int si = c >> 1, ri = c & 1, s = si ? 1 : -1, r = ri ? 1 : -1;
+      const u64 oj = out(j, s), ol = out(l, r);
+      t.q[0][m] = ~oj & ~ol;
+      t.q[1][m] = oj & ~ol;
+      t.q[2][m] = ~oj & ol;
+      t.q[3][m] = oj & ol;
+      t.sh[0][m] = code(sh_in(j, s) + sh_in(l, r));
+      t.sh[1][m] = code(sh_out(j, s) + sh_in(l, r));
+      t.sh[2][m] = code(sh_in(j, s) + sh_out(l, r));
+      t.sh[3][m] = code(sh_out(j, s) + sh_out(l, r));
+      t.tg[m] = static_cast<uint32_t>(1 + 2 * j + si) << 8 | static_cast<uint32_t>(1 + 2 * l + ri) << 16 |
+                static_cast<uint32_t>(1 + 2 * N + 4 * p + 2 * si + ri) << 24;
+      t.src[m] = static_cast<uint32_t>(2 * j + si) | static_cast<uint32_t>(2 * l + ri) << 8;
+    }
   }
+  return t;
 }
-// Fills the table (one workgroup; callers synchronise afterwards).
+template <int N>
+__device__ const MoveTable<N> kMoveTable = make_moves<N>();
+// Copies the table into a workgroup's LDS, a word per thread at a time
+// (callers synchronise afterwards).
 template <int N>
 __device__ __forceinline__ void fill_moves(MoveTable<N>& t) {
-  if (threadIdx.x != 0) return;
-  static_for<2 * N>([&](auto Mc) {
-    constexpr int m = decltype(Mc)::value;
-    move_entry<N, m / 2, m % 2, -1, 0>(t, m);
-  });
-  static_for<N * (N - 1) / 2>([&](auto Pc) {
-    constexpr int p = decltype(Pc)::value, j = pair_j(N, p), l = pair_l(N, p);
-    static_for<4>([&](auto Cc) {
-      constexpr int c = decltype(Cc)::value;
-      move_entry<N, j, (c >> 1), l, (c & 1)>(t, 2 * N + 4 * p + c);
-    });
-  });
+  static_assert(sizeof(MoveTable<N>) % 4 == 0, "whole words");
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(&kMoveTable<N>);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(&t);
+  for (uint32_t i = threadIdx.x; i < sizeof(MoveTable<N>) / 4; i += blockDim.x) dst[i] = src[i];
 }
 
 // Grow in two phases per wave.  Phase one takes the bricks with new sources
