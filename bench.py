@@ -289,9 +289,9 @@ def main():
     ap.add_argument("--loads", type=float, nargs="+", default=[0.5, 1.0, 2.0, 4.0, 8.0],
                     help="serving: offered loads rho = lambda * E[service] of the Poisson sweep")
     ap.add_argument("--serving-precision", type=int, default=0, help="serving: 0 FP64, 1 FP32 form in the pool")
-    ap.add_argument("--max-active", type=int, default=48, help="serving: requests running at once")
+    ap.add_argument("--max-active", type=int, default=96, help="serving: requests running at once")
     ap.add_argument("--pool-gib", type=float, default=160.0, help="serving: arena of the pool")
-    ap.add_argument("--group-size", type=int, default=0, help="serving: requests stepped together (0: the pool's 4)")
+    ap.add_argument("--group-size", type=int, default=8, help="serving: requests stepped together (0: the pool's 4)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-baseline-full", type=int, default=0, metavar="STEPS",
